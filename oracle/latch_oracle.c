@@ -1,0 +1,267 @@
+/*
+ * LATCH oracle: plain, slow CPU implementation of the hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+ * load or call this file; only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark use it.  It shares no code, header, table or
+ * constant generator with the HIP library.
+ *
+ * What it computes (paper: "The CUDA LATCH Binary Descriptor", arXiv 1609.03986):
+ *
+ *   - Eq. 1 (Sec. 3.1): bit t of the descriptor of keypoint p is 1 iff the
+ *     squared Frobenius distance between the anchor patch P_{t,A} and the
+ *     first companion P_{t,1} is strictly larger than the distance between
+ *     P_{t,A} and the second companion P_{t,2}; k x k patches with k = 7 and
+ *     T = 512 triplets (Sec. 3.1, closing paragraph of "The LATCH feature
+ *     descriptor").
+ *   - Sec. 3.2 "Memory optimization": the rotated window around the oriented
+ *     keypoint (x, y, theta) is resampled into an upright square before the
+ *     patches are compared.  The paper does not state the resampling, the
+ *     window size used here (48), the scale handling or the rounding; this
+ *     file fixes them as "rule R" (see oracle_sample_window below), written
+ *     out step by step.
+ *   - Sec. 4 "Descriptor matching on the GPU": exhaustive (brute-force)
+ *     Hamming matching.  k = 2 nearest neighbours, ties to the lowest train
+ *     index, ratio test d1 < ratio * d2 evaluated exactly.
+ *
+ * All arithmetic is integer except the three conversions of rule R steps 1-3,
+ * which are done in IEEE double.  Integer intermediates are kept in int64 so
+ * that no overflow argument is needed here.
+ *
+ * Parity pins: every function is pinned by the CPU tests against closed
+ * forms, invariants and brute force (hand-built tiles, numpy crops, textbook
+ * rotation, full sorts); see the test files named test_oracle_*.py.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_WIN 48          /* upright window side, pixels */
+#define OR_HALF 24         /* window offset: pixel (i, j) sits at (j - 24, i - 24) */
+#define OR_R 3             /* patch radius: 7 x 7 patches */
+#define OR_T 512           /* triplets = bits per descriptor */
+#define OR_WORDS 16        /* 512 bits as 16 little-endian uint32 words */
+#define OR_BINS 4096       /* angle bins of the Q14 rotation table */
+#define OR_Q14 16384.0
+#define OR_NO_NEIGHBOUR_DIST 513
+#define OR_FLAG_BAD_KEYPOINT 1u
+
+/* ------------------------------------------------------------------------ */
+/* Rule R, step 2: the Q14 rotation table.                                   */
+/* ------------------------------------------------------------------------ */
+/*
+ * First octant from libm in double, rounded to nearest-even; the other seven
+ * octants by the exact symmetries cos(90-a) = sin(a) and a rotation by a
+ * quarter turn (C, S) -> (-S, C).  This makes the table exactly symmetric
+ * under 90-degree rotations, which is what makes the descriptor of a
+ * quarter-turned image bit-identical.
+ */
+void oracle_rotation_table(int16_t *cos_q14, int16_t *sin_q14)
+{
+    int16_t c_oct[513], s_oct[513];
+    for (int a = 0; a <= 512; ++a) {
+        double theta = 2.0 * M_PI * (double)a / (double)OR_BINS;
+        c_oct[a] = (int16_t)rint(OR_Q14 * cos(theta));
+        s_oct[a] = (int16_t)rint(OR_Q14 * sin(theta));
+    }
+    for (int a = 0; a < 1024; ++a) {
+        if (a <= 512) {
+            cos_q14[a] = c_oct[a];
+            sin_q14[a] = s_oct[a];
+        } else {
+            cos_q14[a] = s_oct[1024 - a];
+            sin_q14[a] = c_oct[1024 - a];
+        }
+    }
+    for (int a = 1024; a < OR_BINS; ++a) {
+        cos_q14[a] = (int16_t)(-sin_q14[a - 1024]);
+        sin_q14[a] = cos_q14[a - 1024];
+    }
+}
+
+/* Round half away from zero of n / 2^22, for any integer n. */
+static int64_t round_q22(int64_t n)
+{
+    int64_t mag = n < 0 ? -n : n;
+    int64_t r = (mag + ((int64_t)1 << 21)) >> 22;
+    return n < 0 ? -r : r;
+}
+
+static int64_t clamp64(int64_t v, int64_t lo, int64_t hi)
+{
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+/*
+ * Rule R, steps 1-5: resample the 48 x 48 upright window of one keypoint.
+ *
+ *   1. centre  cx = floor(x + 1/2), cy = floor(y + 1/2), in double;
+ *   2. angle   b = rne(angle_deg * (4096/360)) mod 4096, in double;
+ *   3. scale   sq = rne(scale * 256), must lie in [1, 1024];
+ *   4. offsets for window pixel (i, j), u = j - 24, v = i - 24:
+ *        dx = sq * (C[b] u - S[b] v),  dy = sq * (S[b] u + C[b] v)
+ *      and ox, oy = dx, dy / 2^22 rounded half away from zero;
+ *   5. sample  tile[i][j] = img[clamp(cy + oy, 0, H-1) * pitch
+ *                               + clamp(cx + ox, 0, W-1)].
+ *
+ * Returns 0, or OR_FLAG_BAD_KEYPOINT (tile untouched) when the keypoint is
+ * outside the domain of the rule: a non-finite field, |x| or |y| > 2^24,
+ * |angle| > 1e6 degrees, or sq outside [1, 1024].
+ */
+unsigned oracle_sample_window(const uint8_t *img, int height, int width, int pitch,
+                              float x, float y, float angle_deg, float scale,
+                              const int16_t *cos_q14, const int16_t *sin_q14,
+                              uint8_t *tile)
+{
+    if (!isfinite(x) || !isfinite(y) || !isfinite(angle_deg) || !isfinite(scale))
+        return OR_FLAG_BAD_KEYPOINT;
+    if (fabs((double)x) > 16777216.0 || fabs((double)y) > 16777216.0)
+        return OR_FLAG_BAD_KEYPOINT;
+    if (fabs((double)angle_deg) > 1.0e6)
+        return OR_FLAG_BAD_KEYPOINT;
+
+    int64_t cx = (int64_t)floor((double)x + 0.5);
+    int64_t cy = (int64_t)floor((double)y + 0.5);
+
+    int64_t braw = (int64_t)rint((double)angle_deg * (4096.0 / 360.0));
+    int64_t b = ((braw % OR_BINS) + OR_BINS) % OR_BINS;
+
+    int64_t sq = (int64_t)rint((double)scale * 256.0);
+    if (sq < 1 || sq > 1024)
+        return OR_FLAG_BAD_KEYPOINT;
+
+    int64_t c = cos_q14[b], s = sin_q14[b];
+    for (int i = 0; i < OR_WIN; ++i) {
+        for (int j = 0; j < OR_WIN; ++j) {
+            int64_t u = j - OR_HALF, v = i - OR_HALF;
+            int64_t dx = sq * (c * u - s * v);
+            int64_t dy = sq * (s * u + c * v);
+            int64_t X = clamp64(cx + round_q22(dx), 0, width - 1);
+            int64_t Y = clamp64(cy + round_q22(dy), 0, height - 1);
+            tile[i * OR_WIN + j] = img[Y * (int64_t)pitch + X];
+        }
+    }
+    return 0;
+}
+
+/*
+ * Eq. 1 for one triplet on one tile: the two squared Frobenius distances,
+ * summed over the 7 x 7 patches centred on the anchor (rA, cA) and on the
+ * companions (r1, c1), (r2, c2).  trip = {rA, cA, r1, c1, r2, c2}, each in
+ * [3, 44] so that every patch lies inside the 48 x 48 tile.
+ */
+void oracle_triplet_distances(const uint8_t *tile, const uint8_t *trip,
+                              int64_t *dist1, int64_t *dist2)
+{
+    int rA = trip[0], cA = trip[1];
+    int r1 = trip[2], c1 = trip[3];
+    int r2 = trip[4], c2 = trip[5];
+    int64_t s1 = 0, s2 = 0;
+    for (int dr = -OR_R; dr <= OR_R; ++dr) {
+        for (int dc = -OR_R; dc <= OR_R; ++dc) {
+            int64_t a = tile[(rA + dr) * OR_WIN + (cA + dc)];
+            int64_t p = tile[(r1 + dr) * OR_WIN + (c1 + dc)];
+            int64_t q = tile[(r2 + dr) * OR_WIN + (c2 + dc)];
+            s1 += (a - p) * (a - p);
+            s2 += (a - q) * (a - q);
+        }
+    }
+    *dist1 = s1;
+    *dist2 = s2;
+}
+
+/* Eq. 1 applied to all 512 triplets; bit t goes to word t/32, bit t%32. */
+void oracle_describe_tile(const uint8_t *tile, const uint8_t *triplets, uint32_t *desc)
+{
+    memset(desc, 0, OR_WORDS * sizeof(uint32_t));
+    for (int t = 0; t < OR_T; ++t) {
+        int64_t s1, s2;
+        oracle_triplet_distances(tile, triplets + 6 * t, &s1, &s2);
+        if (s1 > s2)
+            desc[t / 32] |= (uint32_t)1 << (t % 32);
+    }
+}
+
+/* Returns 1 if every triplet centre lies in [3, 44], else 0. */
+int oracle_triplets_valid(const uint8_t *triplets)
+{
+    for (int i = 0; i < OR_T * 6; ++i)
+        if (triplets[i] < OR_R || triplets[i] > OR_WIN - 1 - OR_R)
+            return 0;
+    return 1;
+}
+
+/*
+ * Extraction for n keypoints: kps holds n records {x, y, angle_deg, scale}
+ * (float32).  A keypoint outside the domain of rule R gets an all-zero
+ * descriptor and sets bit 0 of the returned flag word.
+ */
+unsigned oracle_extract(const uint8_t *img, int height, int width, int pitch,
+                        const float *kps, int64_t n, const uint8_t *triplets,
+                        uint32_t *desc)
+{
+    int16_t cos_q14[OR_BINS], sin_q14[OR_BINS];
+    oracle_rotation_table(cos_q14, sin_q14);
+    unsigned flags = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : flags)
+    for (int64_t p = 0; p < n; ++p) {
+        uint8_t tile[OR_WIN * OR_WIN];
+        const float *kp = kps + 4 * p;
+        unsigned f = oracle_sample_window(img, height, width, pitch, kp[0], kp[1], kp[2],
+                                          kp[3], cos_q14, sin_q14, tile);
+        if (f) {
+            memset(desc + OR_WORDS * p, 0, OR_WORDS * sizeof(uint32_t));
+            flags |= f;
+        } else {
+            oracle_describe_tile(tile, triplets, desc + OR_WORDS * p);
+        }
+    }
+    return flags;
+}
+
+/* Hamming distance between two 512-bit descriptors. */
+int oracle_hamming(const uint32_t *a, const uint32_t *b)
+{
+    int d = 0;
+    for (int w = 0; w < OR_WORDS; ++w)
+        d += __builtin_popcount(a[w] ^ b[w]);
+    return d;
+}
+
+/*
+ * Brute-force k-NN (k = 1 or 2) under Hamming distance.  For each query the
+ * two lexicographically smallest (distance, train index) pairs are found by
+ * a plain scan in index order.  Missing neighbours (nt < k) get index -1 and
+ * distance 513.  accept[q] = (nt >= 2) && d1 < ratio * d2, exactly (float32
+ * ratio times an integer <= 512 is exact in double).  accept may be NULL.
+ */
+void oracle_knn(const uint32_t *query, int64_t nq, const uint32_t *train, int64_t nt,
+                int k, float ratio, int32_t *idx, int32_t *dist, uint8_t *accept)
+{
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t q = 0; q < nq; ++q) {
+        int64_t j1 = -1, j2 = -1;
+        int d1 = OR_NO_NEIGHBOUR_DIST, d2 = OR_NO_NEIGHBOUR_DIST;
+        for (int64_t j = 0; j < nt; ++j) {
+            int d = oracle_hamming(query + OR_WORDS * q, train + OR_WORDS * j);
+            if (d < d1) {
+                d2 = d1;
+                j2 = j1;
+                d1 = d;
+                j1 = j;
+            } else if (d < d2) {
+                d2 = d;
+                j2 = j;
+            }
+        }
+        idx[q * k] = (int32_t)j1;
+        dist[q * k] = d1;
+        if (k == 2) {
+            idx[q * k + 1] = (int32_t)j2;
+            dist[q * k + 1] = d2;
+        }
+        if (accept)
+            accept[q] = (uint8_t)(nt >= 2 && (double)d1 < (double)ratio * (double)d2);
+    }
+}
