@@ -1,0 +1,161 @@
+/*
+ * latch.h - C ABI of the gfx950 LATCH extraction + Hamming matching library.
+ *
+ * The library computes, on one MI355X (gfx950) GPU:
+ *   - LATCH binary descriptors (paper: "The CUDA LATCH Binary Descriptor",
+ *     arXiv 1609.03986, Sec. 3.1 Eq. 1 and Sec. 3.2): for each oriented,
+ *     scaled keypoint, 512 bits, bit t = [ ||P_A - P_1||^2 > ||P_A - P_2||^2 ]
+ *     over 7 x 7 patches of triplet t inside a 48 x 48 window resampled
+ *     upright around the keypoint;
+ *   - brute-force 2-NN Hamming matching of such descriptors with a ratio
+ *     test (Sec. 4, "Descriptor matching on the GPU").
+ *
+ * Conventions shared by every call:
+ *   - All buffers named *_dev are device pointers owned by the caller; the
+ *     library never frees or retains them past the call's stream work.
+ *   - Every call that takes a stream only enqueues work on that stream and
+ *     returns; results are ready when the stream reaches that point.  No call
+ *     synchronises the stream except latch_check_errors.
+ *   - A handle owns device copies of the rotation table and triplet table,
+ *     a sticky error word and a grow-only workspace.  A handle is not
+ *     thread-safe, and work enqueued through one handle on different streams
+ *     shares its workspace: order such calls yourself or use one handle per
+ *     stream.
+ *   - Return values: LATCH_OK (0) or a negative latch_status.  Host-checkable
+ *     argument errors are reported synchronously and enqueue nothing.
+ *
+ * Resampling rule (the paper states that the rotated window is loaded as an
+ * upright square but not how; this library fixes the rule below, exactly):
+ *   1. cx = floor(x + 1/2), cy = floor(y + 1/2), evaluated in double;
+ *   2. b = rne(angle_deg * (4096/360)) mod 4096 (double multiply, round to
+ *      nearest even), an index into a Q14 table of cos/sin whose first octant
+ *      is rne(16384 cos), rne(16384 sin) of 2 pi a / 4096 and whose other
+ *      octants follow from the exact symmetries (see latch_rotation_table);
+ *   3. sq = rne(scale * 256), which must lie in [1, 1024];
+ *   4. window pixel (i, j), i, j in [0, 47], with u = j - 24, v = i - 24,
+ *      samples offsets ox, oy = sq (C u - S v), sq (S u + C v) divided by 2^22
+ *      and rounded half away from zero;
+ *   5. the sample is img[clamp(cy + oy, 0, H-1) * pitch + clamp(cx + ox, 0, W-1)]
+ *      (clamp-to-edge borders, nearest sampling).
+ * Angles are in degrees and rotate (u right, v down) clockwise on screen.
+ */
+#ifndef LATCH_H
+#define LATCH_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LATCH_WINDOW 48          /* side of the upright window, pixels */
+#define LATCH_PATCH 7            /* patch side k (Sec. 3.1) */
+#define LATCH_TRIPLETS 512       /* bits per descriptor (Sec. 3.1) */
+#define LATCH_DESC_WORDS 16      /* 512 bits as uint32[16]; bit t in word t/32, bit t%32 */
+#define LATCH_ANGLE_BINS 4096
+#define LATCH_NO_NEIGHBOUR_DIST 513
+#define LATCH_MAX_ROWS 2147483647LL
+
+/* Keypoint record, 16 bytes.  Pixel centres are at integer coordinates. */
+typedef struct {
+    float x, y;        /* position in pixels */
+    float angle_deg;   /* orientation, degrees, |angle| <= 1e6 */
+    float scale;       /* window scale; rne(scale * 256) in [1, 1024] */
+} latch_keypoint;
+
+typedef struct latch_ctx *latch_handle;
+
+typedef enum {
+    LATCH_OK = 0,
+    LATCH_EINVAL = -1,   /* bad argument (null pointer, negative or too large size, ...) */
+    LATCH_ENOMEM = -2,   /* device allocation failed */
+    LATCH_EDEVICE = -3,  /* a HIP runtime call failed */
+    LATCH_ERANGE = -4    /* a value outside its documented range (triplet centre, k, ratio) */
+} latch_status;
+
+typedef enum {
+    LATCH_PATH_AUTO = 0,      /* the library chooses */
+    LATCH_PATH_MFMA = 1,      /* int8 MFMA: Hamming = |a| + |b| - 2 a.b over 0/1 bytes */
+    LATCH_PATH_POPCOUNT = 2   /* XOR + popcount */
+} latch_path;
+
+/* Bits of the sticky device error word. */
+#define LATCH_FLAG_BAD_KEYPOINT 1u  /* a keypoint outside rule R's domain; its descriptor is all zero */
+
+/*
+ * Create a handle on the current HIP device.
+ *   triplets_host: host array uint8[512][3][2]: for triplet t, the (row, col)
+ *     window coordinates of the anchor, companion 1 and companion 2 (the order
+ *     of Eq. 1).  Every value must lie in [3, 44] so that each 7 x 7 patch lies
+ *     inside the 48 x 48 window (LATCH_ERANGE otherwise).  Copied; the caller
+ *     keeps ownership.
+ * On success *h receives the handle.  Allocates device memory (LATCH_ENOMEM).
+ */
+int latch_create(latch_handle *h, const uint8_t *triplets_host);
+
+/* Release a handle and its device memory (synchronises the device first).  NULL is a no-op. */
+void latch_destroy(latch_handle h);
+
+/*
+ * Extract LATCH descriptors (Sec. 3.1 Eq. 1; window resampling per rule 1-5 above).
+ *   img_dev:  uint8 image, row-major, height rows of `pitch` bytes (pitch >= width);
+ *             height * pitch must be < 2^31.
+ *   kps_dev:  latch_keypoint[n_kps].
+ *   desc_dev: uint32[n_kps][16] output.
+ * n_kps == 0 is a no-op.  A keypoint outside the rule's domain (non-finite
+ * field, |x| or |y| > 2^24, |angle| > 1e6, rne(scale*256) outside [1, 1024])
+ * gets an all-zero descriptor and sets LATCH_FLAG_BAD_KEYPOINT in the sticky
+ * error word (read it with latch_check_errors).
+ */
+int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                  const latch_keypoint *kps_dev, int64_t n_kps, uint32_t *desc_dev,
+                  hipStream_t stream);
+
+/*
+ * Brute-force k-NN under Hamming distance (Sec. 4, "Descriptor matching on the GPU").
+ *   query_dev: uint32[nq][16], train_dev: uint32[nt][16] descriptors.
+ *   k:         1 or 2 (LATCH_ERANGE otherwise).
+ *   ratio:     in (0, 1] (LATCH_ERANGE otherwise).
+ *   idx_dev, dist_dev: int32[nq][k] outputs: for each query the k
+ *              lexicographically smallest (distance, train index) pairs; ties
+ *              go to the lowest train index.  Missing neighbours (nt < k) get
+ *              index -1 and distance 513.
+ *   accept_dev: uint8[nq] or NULL: 1 iff nt >= 2 and d1 < ratio * d2, evaluated
+ *              exactly (the second neighbour is always searched, also for k = 1).
+ *   path:      a latch_path value; every path returns identical results.
+ * nq == 0 is a no-op.  nq and nt must be < 2^31.  May grow the handle's
+ * workspace (a device allocation, LATCH_ENOMEM on failure).
+ */
+int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
+                const uint32_t *train_dev, int64_t nt, int k, float ratio,
+                int32_t *idx_dev, int32_t *dist_dev, uint8_t *accept_dev, int path,
+                hipStream_t stream);
+
+/*
+ * Read the sticky device error word (LATCH_FLAG_* bits) after all work
+ * enqueued on `stream` so far; synchronises that stream.  If clear != 0 the
+ * word is reset to zero afterwards.
+ */
+int latch_check_errors(latch_handle h, hipStream_t stream, uint32_t *flags_out, int clear);
+
+/* Text of the last error reported through this handle ("" if none).  Valid until the next call. */
+const char *latch_last_error(latch_handle h);
+
+/*
+ * Host-only (no GPU needed): the rotation table of rule step 2, as used by
+ * the kernels.  cos_q14 and sin_q14 receive int16[4096].  For a in [0, 512]:
+ * rne(16384 cos(2 pi a / 4096)) and rne(16384 sin(2 pi a / 4096)); for a in
+ * (512, 1024): (sin, cos) of 1024 - a; every a >= 1024: (C, S)[a] =
+ * (-S, C)[a - 1024].  Returns LATCH_OK or LATCH_EINVAL for NULL pointers.
+ */
+int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
+
+/* Library version string. */
+const char *latch_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LATCH_H */

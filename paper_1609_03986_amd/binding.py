@@ -1,0 +1,205 @@
+"""Thin Python binding over the C ABI of liblatch.so (include/latch.h).
+
+Argument marshalling only: every step of extraction and matching runs in the
+library's HIP kernels.  torch is used for device memory and streams.  The
+binding fails loudly if the library has not been built; there is no CPU
+fallback.
+
+The functions keep the C names:
+    latch_create(triplets) -> handle
+    latch_destroy(handle)
+    latch_extract(handle, img, kps, desc=None, stream=None) -> desc
+    hamming_knn(handle, query, train, k=2, ratio=0.8, path="auto", ...) -> (idx, dist, accept)
+    latch_check_errors(handle, stream=None, clear=True) -> flags
+    latch_rotation_table() -> (cos_q14, sin_q14)   (host only)
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblatch.so")
+
+LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE = 0, -1, -2, -3, -4
+PATHS = {"auto": 0, "mfma": 1, "popcount": 2}
+FLAG_BAD_KEYPOINT = 1
+NO_NEIGHBOUR_DIST = 513
+STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATCH_EDEVICE",
+                -4: "LATCH_ERANGE"}
+
+# Every symbol include/latch.h declares.
+EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "hamming_knn", "latch_check_errors",
+           "latch_last_error", "latch_rotation_table", "latch_version")
+
+
+class LatchError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (STATUS_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def load_library():
+    """Load liblatch.so (built in-tree by paper_1609_03986_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("liblatch.so is not built; run `python -m paper_1609_03986_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, I64, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
+    lib.latch_create.argtypes = [ctypes.POINTER(P), P]
+    lib.latch_create.restype = I
+    lib.latch_destroy.argtypes = [P]
+    lib.latch_destroy.restype = None
+    lib.latch_extract.argtypes = [P, P, I, I, I, P, I64, P, P]
+    lib.latch_extract.restype = I
+    lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
+    lib.hamming_knn.restype = I
+    lib.latch_check_errors.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32), I]
+    lib.latch_check_errors.restype = I
+    lib.latch_last_error.argtypes = [P]
+    lib.latch_last_error.restype = ctypes.c_char_p
+    lib.latch_rotation_table.argtypes = [P, P]
+    lib.latch_rotation_table.restype = I
+    lib.latch_version.argtypes = []
+    lib.latch_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib
+
+
+def _check(h, rc):
+    if rc != LATCH_OK:
+        msg = load_library().latch_last_error(h)
+        raise LatchError(rc, msg.decode() if msg else "")
+
+
+def _stream_ptr(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev(t, dtype, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must have dtype %s, got %s" % (name, dtype, t.dtype))
+    if not t.is_contiguous() and not (name == "img" and t.stride(1) == 1):
+        raise ValueError("%s must be contiguous" % name)
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def latch_rotation_table():
+    """Host-only rotation table of the resampling rule: (cos_q14, sin_q14) int16[4096]."""
+    c = np.zeros(4096, np.int16)
+    s = np.zeros(4096, np.int16)
+    rc = load_library().latch_rotation_table(c.ctypes.data_as(ctypes.c_void_p),
+                                             s.ctypes.data_as(ctypes.c_void_p))
+    _check(None, rc)
+    return c, s
+
+
+def latch_version():
+    return load_library().latch_version().decode()
+
+
+def latch_create(triplets):
+    """Create a handle on the current device from uint8[512, 3, 2] triplets (host)."""
+    trip = np.ascontiguousarray(np.asarray(triplets, np.uint8).reshape(512, 3, 2))
+    h = ctypes.c_void_p()
+    rc = load_library().latch_create(ctypes.byref(h), trip.ctypes.data_as(ctypes.c_void_p))
+    if rc != LATCH_OK:
+        raise LatchError(rc, "latch_create failed")
+    return h
+
+
+def latch_destroy(h):
+    load_library().latch_destroy(h)
+
+
+def latch_extract(h, img, kps, desc=None, stream=None):
+    """Extract descriptors; returns desc, torch.int32 [n, 16] holding the uint32 words.
+
+    img: uint8 [H, W] CUDA tensor; a row stride larger than W is passed as the pitch.
+    kps: float32 [n, 4] CUDA tensor of (x, y, angle_deg, scale).
+    """
+    import torch
+    if img.dim() != 2:
+        raise ValueError("img must be 2-D")
+    if kps.dim() != 2 or kps.shape[1] != 4:
+        raise ValueError("kps must be [n, 4]")
+    n = kps.shape[0]
+    if desc is None:
+        desc = torch.empty((n, 16), dtype=torch.int32, device=kps.device)
+    elif tuple(desc.shape) != (n, 16):
+        raise ValueError("desc must be [n, 16]")
+    H, W = img.shape
+    rc = load_library().latch_extract(h, _dev(img, torch.uint8, "img"), H, W, img.stride(0),
+                                      _dev(kps, torch.float32, "kps"), n,
+                                      _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
+    _check(h, rc)
+    return desc
+
+
+def hamming_knn(h, query, train, k=2, ratio=0.8, path="auto", idx=None, dist=None, accept=None,
+                want_accept=True, stream=None):
+    """Brute-force k-NN.  query [nq, 16], train [nt, 16] int32 (uint32 bit patterns).
+
+    Returns (idx int32 [nq, k], dist int32 [nq, k], accept uint8 [nq] or None)."""
+    import torch
+    nq, nt = query.shape[0], train.shape[0]
+    dev = query.device
+    if idx is None:
+        idx = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if dist is None:
+        dist = torch.empty((nq, k), dtype=torch.int32, device=dev)
+    if accept is None and want_accept:
+        accept = torch.empty((nq,), dtype=torch.uint8, device=dev)
+    acc_ptr = _dev(accept, torch.uint8, "accept") if accept is not None else None
+    tptr = _dev(train, torch.int32, "train") if nt > 0 else None
+    rc = load_library().hamming_knn(h, _dev(query, torch.int32, "query"), nq, tptr, nt, int(k),
+                                    float(ratio), _dev(idx, torch.int32, "idx"),
+                                    _dev(dist, torch.int32, "dist"), acc_ptr, PATHS[path],
+                                    _stream_ptr(stream))
+    _check(h, rc)
+    return idx, dist, accept
+
+
+def latch_check_errors(h, stream=None, clear=True):
+    v = ctypes.c_uint32()
+    rc = load_library().latch_check_errors(h, _stream_ptr(stream), ctypes.byref(v), int(clear))
+    _check(h, rc)
+    return v.value
+
+
+class Latch:
+    """Owning wrapper of a handle (the same calls, with the handle bound)."""
+
+    def __init__(self, triplets):
+        self.h = latch_create(triplets)
+
+    def extract(self, img, kps, desc=None, stream=None):
+        return latch_extract(self.h, img, kps, desc, stream)
+
+    def knn(self, query, train, k=2, ratio=0.8, path="auto", **kw):
+        return hamming_knn(self.h, query, train, k, ratio, path, **kw)
+
+    def check_errors(self, stream=None, clear=True):
+        return latch_check_errors(self.h, stream, clear)
+
+    def close(self):
+        if self.h is not None:
+            latch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,65 @@
+// Library-internal declarations shared by the runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace latch {
+
+// Window geometry.
+constexpr int kWin = 48;                 // upright window side
+constexpr int kHalf = 24;                // pixel (i, j) sits at offset (j - 24, i - 24)
+constexpr int kPatchR = 3;               // 7 x 7 patches
+constexpr int kTriplets = 512;
+constexpr int kWords = 16;
+constexpr int kBins = 4096;
+
+// Extraction LDS layout, per wavefront: four byte-shifted copies of the
+// 48 x 48 u8 window.  Copy s holds, at byte (r * kRowBytes + 4 w + b), window
+// byte (r, 4 w + s + b).  Any 7-byte patch row starting at column c0 is then
+// the first 7 bytes of the two aligned dwords at copy (c0 & 3), column
+// c0 - (c0 & 3).
+constexpr int kRowBytes = 48;
+constexpr int kCopyBytes = kWin * kRowBytes;     // 2304
+constexpr int kWaveLdsBytes = 4 * kCopyBytes;    // 9216
+constexpr int kExtractWaves = 4;                 // wavefronts per workgroup
+
+// Matching.
+constexpr int kTileRows = 32;                    // train rows per MFMA tile
+constexpr int kTileBytes = kTileRows * 512;      // expanded tile: 16 steps x 64 lanes x 16 B
+constexpr int kMaxSplitRows = (1 << 21) - 32;    // split-local train index < 2^21 - 1
+constexpr uint64_t kNoNeighbour = ~0ull;         // partial-result sentinel
+
+struct ExtractArgs {
+    const uint8_t *img;
+    int height, width, pitch;
+    const float4 *kps;
+    int64_t n;
+    const int2 *rot;          // [4096] {cos_q14, sin_q14}
+    const uint2 *trip_off;    // [512] {offA | off1 << 16, off2} LDS byte offsets
+    uint32_t *desc;
+    uint32_t *flags;
+};
+
+hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
+
+struct KnnPlan {
+    int64_t nq, nt;
+    int64_t split_rows;       // multiple of kTileRows, <= kMaxSplitRows
+    int nsplit;
+};
+
+// Expanded-operand prep for the MFMA path (bits -> {0,1} bytes in fragment
+// order, plus per-row key bases).  expanded: ceil(nt/32) * kTileBytes bytes;
+// rowbase: ceil(nt/32) * 32 uint32.
+hipError_t launch_knn_prep(const uint32_t *train, int64_t nt, const KnnPlan &plan,
+                           uint8_t *expanded, uint32_t *rowbase, hipStream_t stream);
+hipError_t launch_knn_mfma(const uint32_t *query, const uint8_t *expanded,
+                           const uint32_t *rowbase, const KnnPlan &plan, uint64_t *partial,
+                           hipStream_t stream);
+hipError_t launch_knn_popcount(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
+                               uint64_t *partial, hipStream_t stream);
+hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k, float ratio,
+                            int32_t *idx, int32_t *dist, uint8_t *accept, hipStream_t stream);
+
+}  // namespace latch

@@ -1,0 +1,279 @@
+// C ABI of the LATCH library: handle, argument checks, tables, workspace and
+// launches.  Every call only enqueues on the caller's stream (see latch.h).
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/latch.h"
+#include "internal.h"
+
+using namespace latch;
+
+struct latch_ctx {
+    int device = 0;
+    int2 *rot_dev = nullptr;           // [4096] {cos_q14, sin_q14}
+    uint2 *trip_off_dev = nullptr;     // [512] LDS byte offsets of the three patches
+    uint32_t *flags_dev = nullptr;     // sticky error word
+    uint8_t *ws = nullptr;             // grow-only workspace
+    size_t ws_bytes = 0;
+    std::string last_error;
+};
+
+namespace {
+
+int fail(latch_handle h, int code, const char *fmt, ...) __attribute__((format(printf, 3, 4)));
+
+int fail(latch_handle h, int code, const char *fmt, ...)
+{
+    if (h) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        h->last_error = buf;
+    }
+    return code;
+}
+
+int hip_fail(latch_handle h, hipError_t e, const char *what)
+{
+    return fail(h, e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+// Rule step 2: the first octant from libm, the rest from the exact
+// symmetries cos(90 - a) = sin(a) and (C, S)(a + 90) = (-S, C)(a).
+void rotation_table(int16_t *c, int16_t *s)
+{
+    const double step = M_PI / 2048.0;
+    for (int a = 0; a <= 512; ++a) {
+        c[a] = (int16_t)std::lrint(16384.0 * std::cos(step * a));
+        s[a] = (int16_t)std::lrint(16384.0 * std::sin(step * a));
+    }
+    for (int a = 513; a < 1024; ++a) {
+        c[a] = s[1024 - a];
+        s[a] = c[1024 - a];
+    }
+    for (int a = 1024; a < kBins; ++a) {
+        c[a] = (int16_t)(-s[a - 1024]);
+        s[a] = c[a - 1024];
+    }
+}
+
+// LDS byte offset of the top-left byte of the 7 x 7 patch centred on (r, c),
+// in the byte-shifted copy that makes its rows dword-aligned.
+uint32_t patch_offset(int r, int c)
+{
+    const int c0 = c - kPatchR;
+    const int shift = c0 & 3;
+    return (uint32_t)(shift * kCopyBytes + (r - kPatchR) * kRowBytes + (c0 - shift));
+}
+
+int ensure_workspace(latch_handle h, size_t need)
+{
+    if (need <= h->ws_bytes) return LATCH_OK;
+    size_t grow = need + need / 4;
+    // Work already enqueued may still use the old buffer.
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
+    if (h->ws) (void)hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+    e = hipMalloc((void **)&h->ws, grow);
+    if (e != hipSuccess) return hip_fail(h, e, "hipMalloc(workspace)");
+    h->ws_bytes = grow;
+    return LATCH_OK;
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+KnnPlan plan_knn(int64_t nq, int64_t nt, int path)
+{
+    KnnPlan p;
+    p.nq = nq;
+    p.nt = nt;
+    const int64_t tiles = (nt + kTileRows - 1) / kTileRows;
+    if (tiles == 0) {
+        p.nsplit = 1;
+        p.split_rows = kTileRows;
+        return p;
+    }
+    const int64_t per_group = path == LATCH_PATH_MFMA ? 256 : 256;
+    const int64_t qgroups = (nq + per_group - 1) / per_group;
+    const int64_t target_groups = path == LATCH_PATH_MFMA ? 1024 : 2048;
+    int64_t nsplit = (target_groups + qgroups - 1) / qgroups;
+    const int64_t max_by_size = (tiles + 7) / 8;              // >= 8 tiles (256 rows) per split
+    if (nsplit > max_by_size) nsplit = max_by_size;
+    if (nsplit < 1) nsplit = 1;
+    const int64_t min_by_index = (nt + kMaxSplitRows - 1) / kMaxSplitRows;
+    if (nsplit < min_by_index) nsplit = min_by_index;
+    if (nsplit > 65535) nsplit = 65535;
+    int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
+    p.split_rows = tiles_per_split * kTileRows;
+    p.nsplit = (int)((tiles + tiles_per_split - 1) / tiles_per_split);
+    return p;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *latch_version(void) { return "latch-gfx950 0.1"; }
+
+int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14)
+{
+    if (!cos_q14 || !sin_q14) return LATCH_EINVAL;
+    rotation_table(cos_q14, sin_q14);
+    return LATCH_OK;
+}
+
+int latch_create(latch_handle *out, const uint8_t *triplets_host)
+{
+    if (!out || !triplets_host) return LATCH_EINVAL;
+    *out = nullptr;
+    for (int i = 0; i < kTriplets * 6; ++i)
+        if (triplets_host[i] < kPatchR || triplets_host[i] > kWin - 1 - kPatchR) return LATCH_ERANGE;
+
+    latch_ctx *h = new latch_ctx();
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return LATCH_EDEVICE;
+    }
+    int16_t c[kBins], s[kBins];
+    rotation_table(c, s);
+    int2 rot[kBins];
+    for (int a = 0; a < kBins; ++a) rot[a] = make_int2(c[a], s[a]);
+    uint2 toff[kTriplets];
+    for (int t = 0; t < kTriplets; ++t) {
+        const uint8_t *tr = triplets_host + 6 * t;
+        toff[t].x = patch_offset(tr[0], tr[1]) | (patch_offset(tr[2], tr[3]) << 16);
+        toff[t].y = patch_offset(tr[4], tr[5]);
+    }
+    int rc = LATCH_OK;
+    if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->trip_off_dev, sizeof toff)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMemcpy(h->rot_dev, rot, sizeof rot, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->trip_off_dev, toff, sizeof toff, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(h->flags_dev, 0, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
+        latch_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return LATCH_OK;
+}
+
+void latch_destroy(latch_handle h)
+{
+    if (!h) return;
+    (void)hipDeviceSynchronize();
+    if (h->rot_dev) (void)hipFree(h->rot_dev);
+    if (h->trip_off_dev) (void)hipFree(h->trip_off_dev);
+    if (h->flags_dev) (void)hipFree(h->flags_dev);
+    if (h->ws) (void)hipFree(h->ws);
+    delete h;
+}
+
+const char *latch_last_error(latch_handle h) { return h ? h->last_error.c_str() : "null handle"; }
+
+int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                  const latch_keypoint *kps_dev, int64_t n_kps, uint32_t *desc_dev,
+                  hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (n_kps < 0 || n_kps > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "n_kps = %lld out of [0, 2^31)", (long long)n_kps);
+    if (height < 1 || width < 1 || pitch < width)
+        return fail(h, LATCH_EINVAL, "bad image shape %d x %d, pitch %d", height, width, pitch);
+    if ((int64_t)height * pitch > (int64_t)INT32_MAX)
+        return fail(h, LATCH_EINVAL, "image of %d rows x %d pitch exceeds 2^31 bytes", height, pitch);
+    if (n_kps == 0) return LATCH_OK;
+    if (!img_dev || !kps_dev || !desc_dev) return fail(h, LATCH_EINVAL, "null buffer");
+    ExtractArgs a;
+    a.img = img_dev;
+    a.height = height;
+    a.width = width;
+    a.pitch = pitch;
+    a.kps = reinterpret_cast<const float4 *>(kps_dev);
+    a.n = n_kps;
+    a.rot = h->rot_dev;
+    a.trip_off = h->trip_off_dev;
+    a.desc = desc_dev;
+    a.flags = h->flags_dev;
+    hipError_t e = launch_extract(a, stream);
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
+}
+
+int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32_t *train_dev,
+                int64_t nt, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                uint8_t *accept_dev, int path, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (nq < 0 || nq > LATCH_MAX_ROWS || nt < 0 || nt > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "sizes nq = %lld, nt = %lld out of [0, 2^31)", (long long)nq,
+                    (long long)nt);
+    if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
+    if (!(ratio > 0.0f && ratio <= 1.0f))
+        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
+    if (path != LATCH_PATH_AUTO && path != LATCH_PATH_MFMA && path != LATCH_PATH_POPCOUNT)
+        return fail(h, LATCH_EINVAL, "unknown path %d", path);
+    if (nq == 0) return LATCH_OK;
+    if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
+        return fail(h, LATCH_EINVAL, "null buffer");
+    if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
+
+    const KnnPlan plan = plan_knn(nq, nt, path);
+    const int64_t tiles = (nt + kTileRows - 1) / kTileRows;
+    const size_t partial_bytes = align_up((size_t)plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
+    size_t expanded_bytes = 0, rowbase_bytes = 0;
+    if (path == LATCH_PATH_MFMA) {
+        expanded_bytes = (size_t)tiles * kTileBytes;
+        rowbase_bytes = align_up((size_t)tiles * kTileRows * sizeof(uint32_t), 256);
+    }
+    int rc = ensure_workspace(h, partial_bytes + expanded_bytes + rowbase_bytes);
+    if (rc != LATCH_OK) return rc;
+    uint64_t *partial = reinterpret_cast<uint64_t *>(h->ws);
+    uint8_t *expanded = h->ws + partial_bytes;
+    uint32_t *rowbase = reinterpret_cast<uint32_t *>(h->ws + partial_bytes + expanded_bytes);
+
+    hipError_t e;
+    if (path == LATCH_PATH_MFMA) {
+        if ((e = launch_knn_prep(train_dev, nt, plan, expanded, rowbase, stream)) != hipSuccess)
+            return hip_fail(h, e, "prep launch");
+        if ((e = launch_knn_mfma(query_dev, expanded, rowbase, plan, partial, stream)) != hipSuccess)
+            return hip_fail(h, e, "mfma launch");
+    } else {
+        if ((e = launch_knn_popcount(query_dev, train_dev, plan, partial, stream)) != hipSuccess)
+            return hip_fail(h, e, "popcount launch");
+    }
+    if ((e = launch_knn_merge(partial, plan, k, ratio, idx_dev, dist_dev, accept_dev, stream)) !=
+        hipSuccess)
+        return hip_fail(h, e, "merge launch");
+    return LATCH_OK;
+}
+
+int latch_check_errors(latch_handle h, hipStream_t stream, uint32_t *flags_out, int clear)
+{
+    if (!h || !flags_out) return LATCH_EINVAL;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, h->flags_dev, sizeof v, hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(h, e, "reading error word");
+    *flags_out = v;
+    if (clear) {
+        e = hipMemsetAsync(h->flags_dev, 0, sizeof v, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(h, e, "clearing error word");
+    }
+    return LATCH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,72 @@
+"""CPU checks of the C ABI: the library loads, exports every symbol declared in
+include/latch.h, rejects host-checkable bad arguments without a GPU, and its
+rotation table equals the oracle's (built independently)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "latch.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1609_03986_amd import binding
+    return binding.load_library()
+
+
+def test_header_declares_the_expected_calls():
+    from paper_1609_03986_amd import binding
+    assert declared_functions() == sorted(binding.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_rotation_table_equals_the_oracle_table():
+    from paper_1609_03986_amd import binding
+    c, s = binding.latch_rotation_table()
+    oc, os_ = oracle.rotation_table()
+    assert np.array_equal(c, oc)
+    assert np.array_equal(s, os_)
+
+
+def test_version_string():
+    from paper_1609_03986_amd import binding
+    assert binding.latch_version().startswith("latch-gfx950")
+
+
+def test_null_handle_and_null_pointer_arguments_are_rejected(lib):
+    from paper_1609_03986_amd import binding
+    assert lib.latch_extract(None, None, 10, 10, 10, None, 1, None, None) == binding.LATCH_EINVAL
+    assert lib.hamming_knn(None, None, 1, None, 1, 2, 0.8, None, None, None, 0, None) == \
+        binding.LATCH_EINVAL
+    assert lib.latch_rotation_table(None, None) == binding.LATCH_EINVAL
+    assert lib.latch_create(None, None) == binding.LATCH_EINVAL
+    v = ctypes.c_uint32()
+    assert lib.latch_check_errors(None, None, ctypes.byref(v), 0) == binding.LATCH_EINVAL
+    lib.latch_destroy(None)                       # no-op
+
+
+def test_out_of_range_triplets_are_rejected_before_touching_the_device(lib, triplets):
+    from paper_1609_03986_amd import binding
+    for bad_val in (2, 45, 255):
+        bad = triplets.copy()
+        bad[100, 2, 1] = bad_val
+        h = ctypes.c_void_p()
+        rc = lib.latch_create(ctypes.byref(h), bad.ctypes.data_as(ctypes.c_void_p))
+        assert rc == binding.LATCH_ERANGE
+        assert not h.value
