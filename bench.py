@@ -1,0 +1,206 @@
+"""Benchmark: LATCH extraction + 2-NN Hamming matching on one MI355X.
+
+One step is one pass of the whole path over one synthetic image pair:
+  extract 10,000 descriptors from each of two 1920x1080 u8 images (angle
+  U[0, 360), scale 1.2^U{0..7}), then match the 10,000 query descriptors 2-NN
+  against the 10,000 train descriptors with ratio 0.8.
+Inputs are resident in HBM before the timed region starts.
+
+Prints one JSON line.  `value` is descriptors extracted and matched per
+second for the whole step (20,000 descriptors per step).  Extra fields give
+the component rates (extraction desc/s, matching pairs/s per path), step
+latency percentiles, per-kernel durations from HIP events recorded by the
+library on its launch stream, the roofline of the dominant kernel and the
+CPU oracle baseline.
+
+    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--path mfma|popcount]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "LATCH desc/s + Hamming pairs/s (MFMA vs popcount) at 1 GPU; p50/p99 ms"
+WORKLOAD = ("1920x1080 u8 image pair, 10,000 keypoints each (angle U[0,360), scale 1.2^U{0..7}), "
+            "512-bit LATCH over 48x48 windows with 7x7 patches, then 10,000 x 10,000 "
+            "brute-force 2-NN Hamming matching with ratio 0.8")
+
+# MI355X published peaks and chip constants.
+PEAK_HBM_GBS = 8000.0
+PEAK_INT8_MFMA_TOPS = 5000.0           # dense int8 MFMA, 10^12 ops/s
+CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
+# Integer VALU with v_dot4_u32_u8: 4 byte MACs = 8 ops per lane per cycle.
+PEAK_DOT4_TOPS = CUS * LANES * CLOCK_GHZ * 8 / 1000.0   # 314.6
+# Algorithmic work ("Roofline accounting").
+EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 3                  # sub, mul, add per squared difference
+MATCH_OPS_PER_PAIR = 512 * 2                             # 512 MACs of a.b
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--path", default="mfma", choices=["mfma", "popcount", "auto"])
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="approximate CPU time budget of the oracle baseline (0 = skip)")
+    return ap.parse_args()
+
+
+def percentile(xs, p):
+    return float(np.percentile(np.asarray(xs), p))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1609_03986_amd import synth
+    from paper_1609_03986_amd.binding import Latch
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    w = synth.workload_hd()
+    trip = synth.triplet_table()
+    nq, nt = len(w["query_kps"]), len(w["train_kps"])
+
+    img_q = torch.from_numpy(w["query_image"]).to(dev)
+    img_t = torch.from_numpy(w["train_image"]).to(dev)
+    kps_q = torch.from_numpy(w["query_kps"]).to(dev)
+    kps_t = torch.from_numpy(w["train_kps"]).to(dev)
+    desc_q = torch.empty((nq, 16), dtype=torch.int32, device=dev)
+    desc_t = torch.empty((nt, 16), dtype=torch.int32, device=dev)
+    idx = torch.empty((nq, 2), dtype=torch.int32, device=dev)
+    dist = torch.empty((nq, 2), dtype=torch.int32, device=dev)
+    acc = torch.empty((nq,), dtype=torch.uint8, device=dev)
+    lat = Latch(trip)
+    stream = torch.cuda.current_stream()
+
+    def extract_both():
+        lat.extract(img_q, kps_q, desc_q)
+        lat.extract(img_t, kps_t, desc_t)
+
+    def match(path):
+        lat.knn(desc_q, desc_t, k=2, ratio=0.8, path=path, idx=idx, dist=dist, accept=acc)
+
+    def step():
+        extract_both()
+        match(args.path)
+
+    def timed_loop(fn, steps, warmup):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        stops = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+        t0 = time.perf_counter()
+        for i in range(steps):
+            starts[i].record(stream)
+            fn()
+            stops[i].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat_ms = [s.elapsed_time(e) for s, e in zip(starts, stops)]
+        return wall, lat_ms
+
+    # --- The timed region: exactly K whole steps. ---
+    wall, step_ms = timed_loop(step, args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    value = (nq + nt) / (wall / args.steps)
+
+    # --- Per-kernel durations from the library's HIP events (same workload). ---
+    lat.timing(True)
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    kernels = {}
+    for name in ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge"):
+        n, total = lat.timing_read(name)
+        if n:
+            kernels[name] = {"launches_per_step": n / args.steps, "avg_ms": total / n,
+                             "ms_per_step": total / args.steps}
+    lat.timing(False)
+
+    # --- Component rates. ---
+    ex_wall, _ = timed_loop(extract_both, args.steps, 2)
+    extract_desc_s = (nq + nt) / (ex_wall / args.steps)
+    pairs = nq * nt
+    match_rates, match_kernel_ms = {}, {}
+    for path in ("mfma", "popcount"):
+        m_wall, _ = timed_loop(lambda: match(path), args.steps, 2)
+        match_rates[path] = pairs / (m_wall / args.steps)
+        lat.timing(True)
+        for _ in range(args.steps):
+            match(path)
+        torch.cuda.synchronize()
+        name = "knn_mfma" if path == "mfma" else "knn_popcount"
+        n, total = lat.timing_read(name)
+        match_kernel_ms[path] = total / max(n, 1)
+        lat.timing(False)
+
+    # --- Roofline of the dominant kernel of the step. ---
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    if dom == "knn_mfma":
+        achieved = pairs * MATCH_OPS_PER_PAIR / (kd["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": PEAK_INT8_MFMA_TOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_INT8_MFMA_TOPS, "traffic": None}
+    elif dom == "extract":
+        per_launch = nq  # both launches carry 10,000 keypoints
+        achieved = per_launch * EXTRACT_OPS_PER_DESC / (kd["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_DOT4_TOPS,
+                "unit": "TFLOP/s", "frac": achieved / PEAK_DOT4_TOPS, "traffic": None}
+    else:  # popcount: 16 xor + 16 popcount-accumulate per pair on the VALU
+        peak = CUS * LANES * CLOCK_GHZ / 1000.0
+        achieved = pairs * 32 / (kd["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak,
+                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+
+    # --- CPU oracle baseline: whole steps on the host cores. ---
+    cpu = None
+    if args.cpu_seconds > 0:
+        import oracle
+        reps, t_cpu = 0, 0.0
+        while t_cpu < args.cpu_seconds and reps < 100:
+            t0 = time.perf_counter()
+            oq, _ = oracle.extract(w["query_image"], w["query_kps"], trip)
+            ot, _ = oracle.extract(w["train_image"], w["train_kps"], trip)
+            oracle.knn(oq, ot, k=2, ratio=0.8)
+            t_cpu += time.perf_counter() - t0
+            reps += 1
+        cpu = {"value": (nq + nt) * reps / t_cpu, "unit": "desc/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": "%d whole steps (2 x 10,000 extractions + 10,000 x 10,000 2-NN) in %.1f s"
+                         % (reps, t_cpu)}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "desc/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "descriptors_per_step": nq + nt, "pairs_per_step": pairs,
+                   "match_path": args.path, "parallelism": "single GPU"},
+        "pairs_per_s": pairs / (wall / args.steps),
+        "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
+        "components": {"extract_desc_per_s": extract_desc_s,
+                       "match_pairs_per_s": match_rates,
+                       "match_kernel_avg_ms": match_kernel_ms},
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    lat.close()
+
+
+if __name__ == "__main__":
+    main()

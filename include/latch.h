@@ -15,7 +15,8 @@
  *     library never frees or retains them past the call's stream work.
  *   - Every call that takes a stream only enqueues work on that stream and
  *     returns; results are ready when the stream reaches that point.  No call
- *     synchronises the stream except latch_check_errors.
+ *     synchronises the stream except latch_check_errors, latch_timing_read,
+ *     latch_destroy and a hamming_knn call that has to grow the workspace.
  *   - A handle owns device copies of the rotation table and triplet table,
  *     a sticky error word and a grow-only workspace.  A handle is not
  *     thread-safe, and work enqueued through one handle on different streams
@@ -81,7 +82,7 @@ typedef enum {
 } latch_path;
 
 /* Bits of the sticky device error word. */
-#define LATCH_FLAG_BAD_KEYPOINT 1u  /* a keypoint outside rule R's domain; its descriptor is all zero */
+#define LATCH_FLAG_BAD_KEYPOINT 1u  /* a keypoint outside the resampling rule's domain; its descriptor is all zero */
 
 /*
  * Create a handle on the current HIP device.
@@ -150,6 +151,18 @@ const char *latch_last_error(latch_handle h);
  * (-S, C)[a - 1024].  Returns LATCH_OK or LATCH_EINVAL for NULL pointers.
  */
 int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
+
+/*
+ * Per-kernel timing with HIP events, for measurement.  While enabled, every
+ * kernel the handle launches is bracketed by two hipEventRecord calls on the
+ * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops
+ * recording).  latch_timing_read waits for the recorded events and returns,
+ * for one kernel name ("extract", "knn_prep", "knn_mfma", "knn_popcount",
+ * "knn_merge"), the number of launches recorded and their summed duration in
+ * milliseconds.  Not for use under stream capture.
+ */
+int latch_timing_enable(latch_handle h, int enable);
+int latch_timing_read(latch_handle h, const char *kernel, int *launches, double *total_ms);
 
 /* Library version string. */
 const char *latch_version(void);

@@ -65,8 +65,15 @@ def _load():
         lib.oracle_hamming.restype = i32
         lib.oracle_knn.argtypes = [P, i64, P, i64, i32, ctypes.c_float, P, P, P]
         lib.oracle_knn.restype = None
+        lib.oracle_num_threads.argtypes = []
+        lib.oracle_num_threads.restype = i32
         _lib = lib
     return _lib
+
+
+def num_threads():
+    """OpenMP threads used by extract() and knn()."""
+    return int(_load().oracle_num_threads())
 
 
 def _ptr(a):

@@ -33,6 +33,7 @@
  * rotation, full sorts); see the test files named test_oracle_*.py.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -264,4 +265,10 @@ void oracle_knn(const uint32_t *query, int64_t nq, const uint32_t *train, int64_
         if (accept)
             accept[q] = (uint8_t)(nt >= 2 && (double)d1 < (double)ratio * (double)d2);
     }
+}
+
+/* Number of OpenMP threads the parallel loops above use. */
+int oracle_num_threads(void)
+{
+    return omp_get_max_threads();
 }

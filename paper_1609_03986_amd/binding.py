@@ -30,7 +30,9 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
 
 # Every symbol include/latch.h declares.
 EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "hamming_knn", "latch_check_errors",
-           "latch_last_error", "latch_rotation_table", "latch_version")
+           "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
+           "latch_timing_read")
+KERNELS = ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge")
 
 
 class LatchError(RuntimeError):
@@ -65,6 +67,11 @@ def load_library():
     lib.latch_last_error.restype = ctypes.c_char_p
     lib.latch_rotation_table.argtypes = [P, P]
     lib.latch_rotation_table.restype = I
+    lib.latch_timing_enable.argtypes = [P, I]
+    lib.latch_timing_enable.restype = I
+    lib.latch_timing_read.argtypes = [P, ctypes.c_char_p, ctypes.POINTER(I),
+                                      ctypes.POINTER(ctypes.c_double)]
+    lib.latch_timing_read.restype = I
     lib.latch_version.argtypes = []
     lib.latch_version.restype = ctypes.c_char_p
     _lib = lib
@@ -178,6 +185,19 @@ def latch_check_errors(h, stream=None, clear=True):
     return v.value
 
 
+def latch_timing_enable(h, enable=True):
+    _check(h, load_library().latch_timing_enable(h, int(bool(enable))))
+
+
+def latch_timing_read(h, kernel):
+    """(launches, total_ms) recorded for one kernel name since timing was enabled."""
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(h, load_library().latch_timing_read(h, kernel.encode(), ctypes.byref(n),
+                                               ctypes.byref(ms)))
+    return n.value, ms.value
+
+
 class Latch:
     """Owning wrapper of a handle (the same calls, with the handle bound)."""
 
@@ -192,6 +212,12 @@ class Latch:
 
     def check_errors(self, stream=None, clear=True):
         return latch_check_errors(self.h, stream, clear)
+
+    def timing(self, enable=True):
+        latch_timing_enable(self.h, enable)
+
+    def timing_read(self, kernel):
+        return latch_timing_read(self.h, kernel)
 
     def close(self):
         if self.h is not None:

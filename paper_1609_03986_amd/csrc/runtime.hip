@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "../../include/latch.h"
 #include "internal.h"
@@ -19,6 +20,14 @@ struct latch_ctx {
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
     std::string last_error;
+    // Event timing (latch_timing_enable).
+    bool timing = false;
+    struct Timed {
+        const char *name;
+        hipEvent_t start, stop;
+    };
+    std::vector<Timed> timed;
+    std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
@@ -86,6 +95,44 @@ int ensure_workspace(latch_handle h, size_t need)
     if (e != hipSuccess) return hip_fail(h, e, "hipMalloc(workspace)");
     h->ws_bytes = grow;
     return LATCH_OK;
+}
+
+hipEvent_t pool_event(latch_handle h)
+{
+    if (!h->event_pool.empty()) {
+        hipEvent_t e = h->event_pool.back();
+        h->event_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Runs one launch, bracketed by events when timing is on.
+template <typename F>
+hipError_t timed_launch(latch_handle h, const char *name, hipStream_t stream, F &&launch)
+{
+    if (!h->timing) return launch();
+    latch_ctx::Timed t{name, pool_event(h), pool_event(h)};
+    if (!t.start || !t.stop) return hipErrorOutOfMemory;
+    hipError_t e = hipEventRecord(t.start, stream);
+    if (e != hipSuccess) return e;
+    e = launch();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(t.stop, stream);
+    if (e != hipSuccess) return e;
+    h->timed.push_back(t);
+    return hipSuccess;
+}
+
+void release_timed(latch_handle h)
+{
+    for (auto &t : h->timed) {
+        h->event_pool.push_back(t.start);
+        h->event_pool.push_back(t.stop);
+    }
+    h->timed.clear();
 }
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
@@ -177,6 +224,8 @@ void latch_destroy(latch_handle h)
     if (h->trip_off_dev) (void)hipFree(h->trip_off_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
     if (h->ws) (void)hipFree(h->ws);
+    release_timed(h);
+    for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
     delete h;
 }
 
@@ -207,7 +256,7 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.trip_off = h->trip_off_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
-    hipError_t e = launch_extract(a, stream);
+    hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
 }
 
@@ -246,17 +295,55 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
 
     hipError_t e;
     if (path == LATCH_PATH_MFMA) {
-        if ((e = launch_knn_prep(train_dev, nt, plan, expanded, rowbase, stream)) != hipSuccess)
-            return hip_fail(h, e, "prep launch");
-        if ((e = launch_knn_mfma(query_dev, expanded, rowbase, plan, partial, stream)) != hipSuccess)
-            return hip_fail(h, e, "mfma launch");
+        e = timed_launch(h, "knn_prep", stream, [&] {
+            return launch_knn_prep(train_dev, nt, plan, expanded, rowbase, stream);
+        });
+        if (e != hipSuccess) return hip_fail(h, e, "prep launch");
+        e = timed_launch(h, "knn_mfma", stream, [&] {
+            return launch_knn_mfma(query_dev, expanded, rowbase, plan, partial, stream);
+        });
+        if (e != hipSuccess) return hip_fail(h, e, "mfma launch");
     } else {
-        if ((e = launch_knn_popcount(query_dev, train_dev, plan, partial, stream)) != hipSuccess)
-            return hip_fail(h, e, "popcount launch");
+        e = timed_launch(h, "knn_popcount", stream, [&] {
+            return launch_knn_popcount(query_dev, train_dev, plan, partial, stream);
+        });
+        if (e != hipSuccess) return hip_fail(h, e, "popcount launch");
     }
-    if ((e = launch_knn_merge(partial, plan, k, ratio, idx_dev, dist_dev, accept_dev, stream)) !=
-        hipSuccess)
-        return hip_fail(h, e, "merge launch");
+    e = timed_launch(h, "knn_merge", stream, [&] {
+        return launch_knn_merge(partial, plan, k, ratio, idx_dev, dist_dev, accept_dev, stream);
+    });
+    if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    return LATCH_OK;
+}
+
+int latch_timing_enable(latch_handle h, int enable)
+{
+    if (!h) return LATCH_EINVAL;
+    if (enable) {
+        // Earlier records must be complete before their events are reused.
+        for (auto &t : h->timed) (void)hipEventSynchronize(t.stop);
+        release_timed(h);
+    }
+    h->timing = enable != 0;
+    return LATCH_OK;
+}
+
+int latch_timing_read(latch_handle h, const char *kernel, int *launches, double *total_ms)
+{
+    if (!h || !kernel || !launches || !total_ms) return LATCH_EINVAL;
+    int n = 0;
+    double ms = 0.0;
+    for (auto &t : h->timed) {
+        if (std::strcmp(t.name, kernel) != 0) continue;
+        hipError_t e = hipEventSynchronize(t.stop);
+        float v = 0.0f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&v, t.start, t.stop);
+        if (e != hipSuccess) return hip_fail(h, e, "reading timing events");
+        ++n;
+        ms += v;
+    }
+    *launches = n;
+    *total_ms = ms;
     return LATCH_OK;
 }
 
