@@ -119,7 +119,7 @@ constexpr int kQueriesPerWave = 32 * kQueryBlocks;
 constexpr int kQueriesPerGroup = kMfmaWaves * kQueriesPerWave;
 constexpr int kTileVec = kTileBytes / 16;              // uint4 per tile (1024)
 
-__global__ __launch_bounds__(kMfmaWaves * 64) void knn_mfma_kernel(
+__global__ __launch_bounds__(kMfmaWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_mfma_kernel(
     const uint32_t *__restrict__ query, int nq, const uint4 *__restrict__ expanded,
     const uint32_t *__restrict__ rowbase, int nt, int split_rows, uint64_t *__restrict__ partial)
 {
