@@ -101,7 +101,8 @@ void latch_destroy(latch_handle h);
 /*
  * Extract LATCH descriptors (Sec. 3.1 Eq. 1; window resampling per rule 1-5 above).
  *   img_dev:  uint8 image, row-major, height rows of `pitch` bytes (pitch >= width);
- *             height * pitch must be < 2^31.
+ *             height and pitch must be < 2^23 and height * pitch < 2^31
+ *             (LATCH_EINVAL otherwise).
  *   kps_dev:  latch_keypoint[n_kps].
  *   desc_dev: uint32[n_kps][16] output.
  * n_kps == 0 is a no-op.  A keypoint outside the rule's domain (non-finite

@@ -14,15 +14,16 @@ constexpr int kTriplets = 512;
 constexpr int kWords = 16;
 constexpr int kBins = 4096;
 
-// Extraction LDS layout, per wavefront: four byte-shifted copies of the
-// 48 x 48 u8 window.  Copy s holds, at byte (r * kRowBytes + 4 w + b), window
-// byte (r, 4 w + s + b).  Any 7-byte patch row starting at column c0 is then
-// the first 7 bytes of the two aligned dwords at copy (c0 & 3), column
-// c0 - (c0 & 3).
+// Extraction LDS layout, per wavefront: eight byte-shifted copies of the
+// 48 x 48 u8 window.  Copy s holds, at byte (r * kRowBytes + x), window byte
+// (r, x + s).  Any 7-byte patch row starting at column c0 is then the first
+// 7 bytes of the 8-byte-aligned quadword at copy (c0 & 7), column c0 - (c0 & 7).
+constexpr int kShiftCopies = 8;
 constexpr int kRowBytes = 48;
-constexpr int kCopyBytes = kWin * kRowBytes;     // 2304
-constexpr int kWaveLdsBytes = 4 * kCopyBytes;    // 9216
-constexpr int kExtractWaves = 4;                 // wavefronts per workgroup
+constexpr int kCopyBytes = kWin * kRowBytes;               // 2304
+constexpr int kWinLdsBytes = kShiftCopies * kCopyBytes;    // 18432 per workgroup
+constexpr int kExtractWaves = 2;                           // wavefronts per workgroup
+constexpr int kLdsPerCu = 160 * 1024;                      // gfx950
 
 // Matching.
 constexpr int kTileRows = 32;                    // train rows per MFMA tile
@@ -39,6 +40,7 @@ struct ExtractArgs {
     const uint2 *trip_off;    // [512] {offA | off1 << 16, off2} LDS byte offsets
     uint32_t *desc;
     uint32_t *flags;
+    int num_cus;
 };
 
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);

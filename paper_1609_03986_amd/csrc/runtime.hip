@@ -14,6 +14,7 @@ using namespace latch;
 
 struct latch_ctx {
     int device = 0;
+    int num_cus = 0;
     int2 *rot_dev = nullptr;           // [4096] {cos_q14, sin_q14}
     uint2 *trip_off_dev = nullptr;     // [512] LDS byte offsets of the three patches
     uint32_t *flags_dev = nullptr;     // sticky error word
@@ -73,11 +74,11 @@ void rotation_table(int16_t *c, int16_t *s)
 }
 
 // LDS byte offset of the top-left byte of the 7 x 7 patch centred on (r, c),
-// in the byte-shifted copy that makes its rows dword-aligned.
+// in the byte-shifted copy that makes its rows 8-byte aligned.
 uint32_t patch_offset(int r, int c)
 {
     const int c0 = c - kPatchR;
-    const int shift = c0 & 3;
+    const int shift = c0 & (kShiftCopies - 1);
     return (uint32_t)(shift * kCopyBytes + (r - kPatchR) * kRowBytes + (c0 - shift));
 }
 
@@ -186,7 +187,9 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
 
     latch_ctx *h = new latch_ctx();
     hipError_t e = hipGetDevice(&h->device);
-    if (e != hipSuccess) {
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess || h->num_cus < 1) {
         delete h;
         return LATCH_EDEVICE;
     }
@@ -241,8 +244,9 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
         return fail(h, LATCH_EINVAL, "n_kps = %lld out of [0, 2^31)", (long long)n_kps);
     if (height < 1 || width < 1 || pitch < width)
         return fail(h, LATCH_EINVAL, "bad image shape %d x %d, pitch %d", height, width, pitch);
-    if ((int64_t)height * pitch > (int64_t)INT32_MAX)
-        return fail(h, LATCH_EINVAL, "image of %d rows x %d pitch exceeds 2^31 bytes", height, pitch);
+    if ((int64_t)height * pitch > (int64_t)INT32_MAX || height >= (1 << 23) || pitch >= (1 << 23))
+        return fail(h, LATCH_EINVAL, "image of %d rows x %d pitch: need rows, pitch < 2^23 and "
+                    "rows * pitch < 2^31", height, pitch);
     if (n_kps == 0) return LATCH_OK;
     if (!img_dev || !kps_dev || !desc_dev) return fail(h, LATCH_EINVAL, "null buffer");
     ExtractArgs a;
@@ -256,6 +260,7 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.trip_off = h->trip_off_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
+    a.num_cus = h->num_cus;
     hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
 }
