@@ -37,7 +37,8 @@ PEAK_INT8_MFMA_TOPS = 5000.0           # dense int8 MFMA, 10^12 ops/s
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
 # Integer VALU with v_dot4_u32_u8: 4 byte MACs = 8 ops per lane per cycle.
 PEAK_DOT4_TOPS = CUS * LANES * CLOCK_GHZ * 8 / 1000.0   # 314.6
-# Algorithmic work ("Roofline accounting").
+# Algorithmic work per unit: per descriptor, 512 triplets x 2 distances x 49 squared
+# differences x 3 integer ops; per matched pair, the 512 MACs of a.b.
 EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 3                  # sub, mul, add per squared difference
 MATCH_OPS_PER_PAIR = 512 * 2                             # 512 MACs of a.b
 
@@ -50,7 +51,21 @@ def parse():
     ap.add_argument("--path", default="mfma", choices=["mfma", "popcount", "auto"])
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
                     help="approximate CPU time budget of the oracle baseline (0 = skip)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
+                         "its FETCH_SIZE / WRITE_SIZE readings calibrate the HBM traffic counters")
     return ap.parse_args()
+
+
+def copy_calibration(mib):
+    import torch
+    x = torch.full((mib << 20,), 7, dtype=torch.uint8, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_mib": mib, "bytes": mib << 20}), flush=True)
 
 
 def percentile(xs, p):
@@ -63,6 +78,9 @@ def main():
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
               "(requested --gpus %d)." % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
 
     import torch
     from paper_1609_03986_amd import synth

@@ -83,6 +83,16 @@ typedef enum {
 
 /* Bits of the sticky device error word. */
 #define LATCH_FLAG_BAD_KEYPOINT 1u  /* a keypoint outside the resampling rule's domain; its descriptor is all zero */
+#define LATCH_FLAG_BAD_IMAGE 2u     /* batched extraction: image id out of range or malformed image entry */
+
+/* One image of a batched extraction (device memory), 24 bytes. */
+typedef struct {
+    const uint8_t *img;   /* device pointer: row-major u8 image */
+    int32_t height;       /* rows, in [1, 2^23) */
+    int32_t width;        /* columns, >= 1 */
+    int32_t pitch;        /* bytes per row, in [width, 2^23); height * pitch < 2^31 */
+    int32_t reserved;     /* set to 0 */
+} latch_image;
 
 /*
  * Create a handle on the current HIP device.
@@ -113,6 +123,27 @@ void latch_destroy(latch_handle h);
 int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
                   const latch_keypoint *kps_dev, int64_t n_kps, uint32_t *desc_dev,
                   hipStream_t stream);
+
+/*
+ * Batched extraction: keypoints of many images of uneven size and count in
+ * one launch (Sec. 4 "CUDA Integration" runs several images concurrently on
+ * streams; here they share one persistent grid).  Same rule and result per
+ * keypoint as latch_extract on its own image.
+ *   images_dev:   latch_image[n_images], device memory (the caller's work list).
+ *   image_id_dev: int32[max_kps], device memory: image of each keypoint.
+ *   kps_dev:      latch_keypoint[max_kps]; desc_dev: uint32[max_kps][16].
+ *   n_kps_dev:    NULL (process max_kps keypoints) or a device int64 holding
+ *                 the count to process this time, capped at max_kps.  With it,
+ *                 a captured HIP graph can be replayed over new batch contents.
+ * A keypoint whose image id is outside [0, n_images), or whose image entry
+ * violates the limits above or has a NULL pointer, gets an all-zero
+ * descriptor and sets LATCH_FLAG_BAD_IMAGE.  Host-checked: max_kps in
+ * [0, 2^31), n_images >= 1 when max_kps > 0, non-NULL buffers (LATCH_EINVAL).
+ */
+int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_images,
+                        const int32_t *image_id_dev, const latch_keypoint *kps_dev,
+                        int64_t max_kps, const int64_t *n_kps_dev, uint32_t *desc_dev,
+                        hipStream_t stream);
 
 /*
  * Brute-force k-NN under Hamming distance (Sec. 4, "Descriptor matching on the GPU").

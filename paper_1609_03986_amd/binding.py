@@ -24,12 +24,14 @@ LIB_PATH = os.path.join(_HERE, "liblatch.so")
 LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE = 0, -1, -2, -3, -4
 PATHS = {"auto": 0, "mfma": 1, "popcount": 2}
 FLAG_BAD_KEYPOINT = 1
+FLAG_BAD_IMAGE = 2
 NO_NEIGHBOUR_DIST = 513
 STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATCH_EDEVICE",
                 -4: "LATCH_ERANGE"}
 
 # Every symbol include/latch.h declares.
-EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "hamming_knn", "latch_check_errors",
+EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "hamming_knn",
+           "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
 KERNELS = ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge")
@@ -59,6 +61,8 @@ def load_library():
     lib.latch_destroy.restype = None
     lib.latch_extract.argtypes = [P, P, I, I, I, P, I64, P, P]
     lib.latch_extract.restype = I
+    lib.latch_extract_batch.argtypes = [P, P, I, P, P, I64, P, P, P]
+    lib.latch_extract_batch.restype = I
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
     lib.hamming_knn.restype = I
     lib.latch_check_errors.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32), I]
@@ -154,6 +158,42 @@ def latch_extract(h, img, kps, desc=None, stream=None):
     return desc
 
 
+IMAGE_ENTRY_BYTES = 24
+
+
+def image_table(images):
+    """Pack device images (uint8 CUDA tensors [H, W], row stride = pitch) into a
+    latch_image table: a uint8 CUDA tensor of n * 24 bytes."""
+    import torch
+    rows = np.zeros((len(images), 3), np.int64)
+    for i, img in enumerate(images):
+        if img.dim() != 2 or img.dtype != torch.uint8 or not img.is_cuda or img.stride(1) != 1:
+            raise TypeError("images must be 2-D uint8 CUDA tensors with unit column stride")
+        H, W = img.shape
+        rows[i, 0] = img.data_ptr()
+        rows[i, 1] = H | (W << 32)
+        rows[i, 2] = img.stride(0)
+    return torch.from_numpy(rows.view(np.uint8).reshape(-1)).to(images[0].device)
+
+
+def latch_extract_batch(h, table, n_images, image_id, kps, desc=None, n_kps=None, stream=None):
+    """Batched extraction.  table: from image_table(); image_id: int32 [n] CUDA;
+    kps: float32 [n, 4] CUDA; n_kps: optional int64 [1] CUDA tensor (count to process)."""
+    import torch
+    n = kps.shape[0]
+    if image_id.shape[0] != n:
+        raise ValueError("image_id must have one entry per keypoint")
+    if desc is None:
+        desc = torch.empty((n, 16), dtype=torch.int32, device=kps.device)
+    nptr = _dev(n_kps, torch.int64, "n_kps") if n_kps is not None else None
+    rc = load_library().latch_extract_batch(h, _dev(table, torch.uint8, "table"), int(n_images),
+                                            _dev(image_id, torch.int32, "image_id"),
+                                            _dev(kps, torch.float32, "kps"), n, nptr,
+                                            _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
+    _check(h, rc)
+    return desc
+
+
 def hamming_knn(h, query, train, k=2, ratio=0.8, path="auto", idx=None, dist=None, accept=None,
                 want_accept=True, stream=None):
     """Brute-force k-NN.  query [nq, 16], train [nt, 16] int32 (uint32 bit patterns).
@@ -206,6 +246,9 @@ class Latch:
 
     def extract(self, img, kps, desc=None, stream=None):
         return latch_extract(self.h, img, kps, desc, stream)
+
+    def extract_batch(self, table, n_images, image_id, kps, desc=None, n_kps=None, stream=None):
+        return latch_extract_batch(self.h, table, n_images, image_id, kps, desc, n_kps, stream)
 
     def knn(self, query, train, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn(self.h, query, train, k, ratio, path, **kw)

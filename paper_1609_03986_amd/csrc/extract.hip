@@ -75,13 +75,26 @@ __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc)
     return __builtin_amdgcn_udot4(a, b, acc, false);
 }
 
-// Rule steps 1-3 for one keypoint (uniform across the workgroup).
+// Rule steps 1-3 for one keypoint (uniform across the workgroup), with the
+// image it samples.
 struct Keypoint {
     bool ok;        // inside the rule's domain (and a real keypoint)
     bool interior;  // every sample lies inside the image: no clamping needed
     int cx, cy;
     int c, s, sq;   // C[b], S[b] (Q14) and the Q8 scale
     int ca, sb;     // sq * C[b], sq * S[b]
+    const uint8_t *img;
+    int height, width, pitch;
+};
+
+// Where keypoints find their image: one image given by value, or a device
+// table of images indexed by a per-keypoint image id.
+struct ImageSource {
+    const uint8_t *img;          // single image
+    int height, width, pitch;
+    const ImageEntry *table;     // batch: table[image_id[k]]
+    const int32_t *image_id;
+    int n_images;
 };
 
 // Rule steps 1-3 for 64 keypoints at once: lane j takes keypoint
@@ -91,19 +104,40 @@ struct Keypoint {
 struct KeypointBatch {
     int cx, cy;
     int cs;          // C[b] & 0xffff | S[b] << 16
-    int sq_flags;    // sq | ok << 16 | interior << 17
+    int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18
+    int img_lo, img_hi;
+    int height, width, pitch;
 };
 
+template <bool kTable>
 __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict__ kps, int64_t n,
                                                        int64_t first, int64_t stride, int lane,
-                                                       const int2 *__restrict__ rot, int height,
-                                                       int width)
+                                                       const int2 *__restrict__ rot,
+                                                       const ImageSource &src)
 {
     KeypointBatch kb;
     const int64_t idx = first + stride * lane;
     const bool real = idx < n;
+    const uint8_t *img = src.img;
+    int height = src.height, width = src.width, pitch = src.pitch;
+    bool image_ok = true;
+    if (kTable) {
+        const int id = real ? src.image_id[idx] : 0;
+        image_ok = id >= 0 && id < src.n_images;
+        const ImageEntry e = image_ok ? src.table[id] : ImageEntry{nullptr, 1, 1, 1, 0};
+        img = e.img;
+        height = e.height;
+        width = e.width;
+        pitch = e.pitch;
+        image_ok = image_ok && img != nullptr && height >= 1 && width >= 1 && pitch >= width &&
+                   height < (1 << 23) && pitch < (1 << 23) &&
+                   (int64_t)height * pitch <= (int64_t)0x7fffffff;
+        if (!image_ok) {
+            height = width = pitch = 1;
+        }
+    }
     const float4 kp = real ? kps[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
-    bool ok = real && __builtin_isfinite(kp.x) && __builtin_isfinite(kp.y) &&
+    bool ok = real && image_ok && __builtin_isfinite(kp.x) && __builtin_isfinite(kp.y) &&
               __builtin_isfinite(kp.z) && __builtin_isfinite(kp.w);
     ok = ok && fabsf(kp.x) <= 16777216.0f && fabsf(kp.y) <= 16777216.0f && fabsf(kp.z) <= 1.0e6f;
     const double sqd = ok ? rint((double)kp.w * 256.0) : 0.0;
@@ -123,11 +157,16 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
     kb.cx = cx;
     kb.cy = cy;
     kb.cs = (cs.x & 0xffff) | (cs.y << 16);
-    kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17);
+    kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18);
+    kb.img_lo = (int)(uint32_t)reinterpret_cast<uintptr_t>(img);
+    kb.img_hi = (int)(uint32_t)(reinterpret_cast<uintptr_t>(img) >> 32);
+    kb.height = height;
+    kb.width = width;
+    kb.pitch = pitch;
     return kb;
 }
 
-__device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j)
+__device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bool *bad_image)
 {
     Keypoint k;
     k.cx = __builtin_amdgcn_readlane(kb.cx, j);
@@ -139,8 +178,15 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j)
     k.sq = f & 0xffff;
     k.ok = (f >> 16) & 1;
     k.interior = (f >> 17) & 1;
+    *bad_image = (f >> 18) & 1;
     k.ca = k.sq * k.c;     // |ca|, |sb| <= 2^24
     k.sb = k.sq * k.s;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane(kb.img_lo, j);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane(kb.img_hi, j);
+    k.img = reinterpret_cast<const uint8_t *>(lo | (hi << 32));
+    k.height = __builtin_amdgcn_readlane(kb.height, j);
+    k.width = __builtin_amdgcn_readlane(kb.width, j);
+    k.pitch = __builtin_amdgcn_readlane(kb.pitch, j);
     return k;
 }
 
@@ -161,11 +207,12 @@ __device__ __forceinline__ void thread_coords(int tid, int (&uv)[kGatherPerThrea
 // dword m exists for m < 4, and for m = 4 in the first wavefront only.
 // sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
 // sq <= 2^10, so every product is exact and full rate.
-__device__ __forceinline__ void issue_gather(const uint8_t *__restrict__ img, int height, int width,
-                                             int pitch, const Keypoint &k, bool has_last,
+__device__ __forceinline__ void issue_gather(const Keypoint &k, bool has_last,
                                              const int (&uv)[kGatherPerThread],
                                              uint32_t (&g)[kSamples])
 {
+    const uint8_t *__restrict__ img = k.img;
+    const int height = k.height, width = k.width, pitch = k.pitch;
 #pragma unroll
     for (int m = 0; m < kGatherPerThread; ++m) {
         if (m == kGatherPerThread - 1 && !has_last) break;
@@ -231,10 +278,10 @@ __device__ __forceinline__ bool triplet_bit(const Rows &r)
     return (int)(q1 - 2u * ac1) > (int)(q2 - 2u * ac2);
 }
 
+template <bool kTable>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void extract_kernel(
-    const uint8_t *__restrict__ img, int height, int width, int pitch,
-    const float4 *__restrict__ kps, int64_t n, const int2 *__restrict__ rot,
-    const uint2 *__restrict__ trip_off, uint32_t *__restrict__ desc,
+    ImageSource src, const float4 *__restrict__ kps, int64_t n_host, const int64_t *__restrict__ n_dev,
+    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off, uint32_t *__restrict__ desc,
     uint32_t *__restrict__ flags)
 {
     __shared__ __attribute__((aligned(16))) uint32_t win[kWinLdsBytes / 4];
@@ -254,21 +301,25 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         off_2[r] = o.y;
     }
 
+    // Keypoint count: a host value, or (batches) a device value capped by it.
+    int64_t n = n_host;
+    if (n_dev) n = min(n, *n_dev);
     int64_t p = blockIdx.x;
     if (p >= n) return;
     const int64_t stride = gridDim.x;
     int uv[kGatherPerThread];
     thread_coords(tid, uv);
     uint32_t g[kSamples];
-    KeypointBatch batch = prepare_batch(kps, n, p, stride, lane, rot, height, width);
-    Keypoint cur = batch_get(batch, 0);
-    if (cur.ok) issue_gather(img, height, width, pitch, cur, has_last, uv, g);
+    KeypointBatch batch = prepare_batch<kTable>(kps, n, p, stride, lane, rot, src);
+    bool bad_image = false;
+    Keypoint cur = batch_get(batch, 0, &bad_image);
+    if (cur.ok) issue_gather(cur, has_last, uv, g);
 
     for (int i = 0; p < n; ++i, p += stride) {
         const bool compute = cur.ok;
         if (!compute) {
             if (tid < kWords) desc[p * kWords + tid] = 0u;
-            if (tid == 0) atomicOr(flags, 1u);
+            if (tid == 0) atomicOr(flags, bad_image ? kFlagBadImage : kFlagBadKeypoint);
         } else {
             // Copy 0: the window itself, row pitch 48 bytes.
             uint32_t w[kGatherPerThread];
@@ -304,9 +355,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 
         // Start the next keypoint's gather; it completes during the arithmetic below.
         const int j = (i + 1) & 63;
-        if (j == 0) batch = prepare_batch(kps, n, p + stride, stride, lane, rot, height, width);
-        cur = batch_get(batch, j);
-        if (cur.ok) issue_gather(img, height, width, pitch, cur, has_last, uv, g);
+        if (j == 0) batch = prepare_batch<kTable>(kps, n, p + stride, stride, lane, rot, src);
+        cur = batch_get(batch, j, &bad_image);
+        if (cur.ok) issue_gather(cur, has_last, uv, g);
         if (!compute) continue;
 
         // Eq. 1 for this wavefront's 256 triplets.
@@ -332,9 +383,13 @@ hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream)
     int64_t blocks = a.n;
     const int64_t resident = (int64_t)a.num_cus * (kLdsPerCu / kWinLdsBytes);
     if (blocks > resident) blocks = resident;
-    hipLaunchKernelGGL(extract_kernel, dim3((unsigned)blocks), dim3(kThreads), 0, stream, a.img,
-                       a.height, a.width, a.pitch, a.kps, a.n, a.rot, a.trip_off, a.desc,
-                       a.flags);
+    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
+    if (a.table)
+        hipLaunchKernelGGL(extract_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.desc, a.flags);
+    else
+        hipLaunchKernelGGL(extract_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.desc, a.flags);
     return hipGetLastError();
 }
 

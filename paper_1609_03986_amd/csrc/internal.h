@@ -31,11 +31,26 @@ constexpr int kTileBytes = kTileRows * 512;      // expanded tile: 16 steps x 64
 constexpr int kMaxSplitRows = (1 << 21) - 32;    // split-local train index < 2^21 - 1
 constexpr uint64_t kNoNeighbour = ~0ull;         // partial-result sentinel
 
-struct ExtractArgs {
+// Sticky error-word bits (same values as the LATCH_FLAG_* of the C ABI).
+constexpr uint32_t kFlagBadKeypoint = 1u;
+constexpr uint32_t kFlagBadImage = 2u;
+
+// Layout-compatible with latch_image of the C ABI.
+struct ImageEntry {
     const uint8_t *img;
+    int32_t height, width, pitch, reserved;
+};
+static_assert(sizeof(ImageEntry) == 24, "latch_image layout");
+
+struct ExtractArgs {
+    const uint8_t *img;            // single image (table == nullptr)
     int height, width, pitch;
+    const ImageEntry *table;       // batch: image table and per-keypoint image ids
+    const int32_t *image_id;
+    int n_images;
     const float4 *kps;
-    int64_t n;
+    int64_t n;                     // keypoints (upper bound when n_dev is set)
+    const int64_t *n_dev;          // optional device-side keypoint count
     const int2 *rot;          // [4096] {cos_q14, sin_q14}
     const uint2 *trip_off;    // [512] {offA | off1 << 16, off2} LDS byte offsets
     uint32_t *desc;
@@ -51,14 +66,8 @@ struct KnnPlan {
     int nsplit;
 };
 
-// Expanded-operand prep for the MFMA path (bits -> {0,1} bytes in fragment
-// order, plus per-row key bases).  expanded: ceil(nt/32) * kTileBytes bytes;
-// rowbase: ceil(nt/32) * 32 uint32.
-hipError_t launch_knn_prep(const uint32_t *train, int64_t nt, const KnnPlan &plan,
-                           uint8_t *expanded, uint32_t *rowbase, hipStream_t stream);
-hipError_t launch_knn_mfma(const uint32_t *query, const uint8_t *expanded,
-                           const uint32_t *rowbase, const KnnPlan &plan, uint64_t *partial,
-                           hipStream_t stream);
+hipError_t launch_knn_mfma(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
+                           uint64_t *partial, hipStream_t stream);
 hipError_t launch_knn_popcount(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
                                uint64_t *partial, hipStream_t stream);
 hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k, float ratio,

@@ -5,9 +5,9 @@
 //
 //   MFMA.  With a, b in {0,1}^512, Hamming(a, b) = |a| + |b| - 2 a.b, and a.b
 //   over all pairs is an int8 x int8 -> int32 matrix product with K = 512.
-//   A prep kernel expands train bits to 0/1 bytes in the exact fragment
-//   order of v_mfma_i32_32x32x32_i8 (one 16 KB tile per 32 train rows), so
-//   the main kernel streams tiles HBM -> LDS -> MFMA with contiguous,
+//   Packed train tiles (32 rows, 2 KB) are expanded to 0/1 bytes in the exact
+//   fragment order of v_mfma_i32_32x32x32_i8 while being staged in LDS, so
+//   HBM carries packed bits only and the MFMA operands come from contiguous,
 //   conflict-free ds_read_b128.  Queries stay resident in VGPRs (64 queries,
 //   128 VGPRs per wavefront).  The sum is exact in int32 (<= 512).
 //
@@ -55,76 +55,85 @@ __device__ __forceinline__ v4i expand16(uint32_t x)
 }
 
 // ---------------------------------------------------------------------------
-// MFMA operand prep.
+// MFMA matcher.  Workgroup = 4 wavefronts x 64 queries; grid (query groups,
+// train splits).
 //
-// Fragment order: for tile tau (train rows 32 tau .. 32 tau + 31), step s
-// (0..15) and lane l (0..63), the 16 bytes at tau * 16384 + s * 1024 + l * 16
-// are bits 32 s + 16 (l / 32) + m, m = 0..15, of train row 32 tau + (l % 32),
-// as 0/1 bytes.  Query fragments use the same bit -> (step, lane, byte) map,
-// so the MFMA's k-summation covers every bit exactly once whatever its
-// internal k order.  Rows beyond nt are zero.
+// Operands.  Train bits enter as bytes b_k in {0, 1} (operand A), query bits
+// as signed bytes 2 a_k - 1 in {-1, +1} (operand B, resident in VGPRs), so the
+// int8 MFMA sum over K = 512 is directly
+//   s = sum_k (2 a_k - 1) b_k = 2 a.b - |b| = |a| - Hamming(a, b),
+// exact in int32, and no train-side popcount is needed.
 //
-// rowbase[j] = ((512 - |t_j|) << 21) + (2^21 - 1 - (j mod split_rows)) for
-// j < nt, 0 beyond: the constant part of the match key (see knn_mfma_kernel).
-// ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void knn_prep_kernel(const uint32_t *__restrict__ train,
-                                                        int nt, int split_rows,
-                                                        uint4 *__restrict__ expanded,
-                                                        uint32_t *__restrict__ rowbase)
-{
-    const int tile = blockIdx.x;
-    const int t = threadIdx.x;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int f = t + 256 * i;          // fragment index within the tile
-        const int s = f >> 6;
-        const int l = f & 63;
-        const int row = tile * kTileRows + (l & 31);
-        uint32_t x = 0;
-        if (row < nt) x = (train[(size_t)row * kWords + s] >> (16 * (l >> 5))) & 0xffffu;
-        const v4i e = expand16(x);
-        expanded[(size_t)tile * (kTileBytes / 16) + f] = make_uint4(e[0], e[1], e[2], e[3]);
-    }
-    if (t < kTileRows) {
-        const int row = tile * kTileRows + t;
-        uint32_t base = 0;
-        if (row < nt) {
-            uint32_t pc = 0;
-#pragma unroll
-            for (int w = 0; w < kWords; ++w) pc += __popc(train[(size_t)row * kWords + w]);
-            const uint32_t local = (uint32_t)(row % split_rows);
-            base = ((512u - pc) << kLocalBits) + (kLocalMask - local);
-        }
-        rowbase[row] = base;
-    }
-}
-
-// ---------------------------------------------------------------------------
-// MFMA matcher.  Workgroup = 4 wavefronts x 64 queries; grid (query blocks,
-// splits).  For train row j (split-local index jl) and a query,
-//   key = (a.b << 22) + rowbase[j] = ((2 a.b + 512 - |b|) << 21) + (2^21 - 1 - jl),
-// and 2 a.b - |b| = |a| - Hamming(a, b), so for a fixed query the largest key
-// is the smallest (distance, index).  Key 0 only arises for padding rows
-// (split-local indices stay below 2^21 - 1), so 0 means "no neighbour".
+// Fragment order.  For a 32-row train tile, step s (0..15) and lane l
+// (0..63), the A fragment is 16 bytes: bits 32 s + 16 (l / 32) + m, m = 0..15,
+// of tile row l % 32.  Query fragments use the same bit -> (step, lane, byte)
+// map, so the MFMA k-sum covers every bit exactly once whatever its internal k
+// order.  Each tile is expanded from its packed 2 KB into this order while
+// being staged in LDS (16 KB) and read back with contiguous, conflict-free
+// ds_read_b128.
+//
+// Keys.  For train row j with split-local index jl,
+//   key = ((s + 512) << 21) + (2^21 - 1 - jl),   s + 512 in [0, 1024],
+// so for a fixed query the largest key is the smallest (distance, index).
+// Split-local indices stay below 2^21 - 1, so a real key is never 0; rows
+// past nt (only in the last tile) are forced to key 0 = "no neighbour".
 //
 // Accumulator layout of v_mfma_i32_32x32x32_i8 (output 32 x 32, 16 values
 // per lane): lane l holds column l % 32 and rows 8 (r / 4) + 4 (l / 32) + r % 4
-// for r = 0..15.  Train rows are the MFMA rows (operand A, streamed from LDS)
-// and queries the columns (operand B, resident), so each lane keeps a
-// running top-2 for one query; lanes l and l ^ 32 merge at the end.
+// for r = 0..15.  Train rows are the MFMA rows and queries the columns, so
+// each lane keeps a running top-2 for one query; lanes l and l ^ 32 merge at
+// the end.
 // ---------------------------------------------------------------------------
 constexpr int kMfmaWaves = 4;
+constexpr int kMfmaThreads = kMfmaWaves * 64;
 constexpr int kQueryBlocks = 2;                        // 32-query blocks per wavefront
 constexpr int kQueriesPerWave = 32 * kQueryBlocks;
 constexpr int kQueriesPerGroup = kMfmaWaves * kQueriesPerWave;
-constexpr int kTileVec = kTileBytes / 16;              // uint4 per tile (1024)
+constexpr int kTileVec = kTileBytes / 16;              // 16-byte fragments per tile (1024)
+static_assert(kMfmaThreads == 8 * kTileRows, "staging: 8 threads per tile row");
 
-__global__ __launch_bounds__(kMfmaWaves * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void knn_mfma_kernel(
-    const uint32_t *__restrict__ query, int nq, const uint4 *__restrict__ expanded,
-    const uint32_t *__restrict__ rowbase, int nt, int split_rows, uint64_t *__restrict__ partial)
+// 16 bits -> 16 signed bytes, +1 for a set bit and -1 for a clear one: byte
+// b in {0, 1} becomes 0xff ^ 0xfe b, and 0xfe b = (b << 8) - (b << 1) stays
+// inside its own byte, so the whole dword is ~((x << 8) - (x << 1)) mod 2^32.
+__device__ __forceinline__ v4i expand16_pm1(uint32_t x)
+{
+    v4i r = expand16(x);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const uint32_t b = (uint32_t)r[i];
+        r[i] = (int)~((b << 8) - (b << 1));
+    }
+    return r;
+}
+
+// Staging role of a thread: tile row tid % 32, packed words 2 (tid / 32) and
+// 2 (tid / 32) + 1, i.e. steps 2 (tid / 32) + {0, 1}, both halves.
+__device__ __forceinline__ uint2 load_tile(const uint32_t *__restrict__ train, int nt, int tile,
+                                           int tid)
+{
+    const int row = tile * kTileRows + (tid & 31);
+    return row < nt ? reinterpret_cast<const uint2 *>(train + (size_t)row * kWords)[tid >> 5]
+                    : make_uint2(0, 0);
+}
+
+__device__ __forceinline__ void stage_tile(uint2 w, int tid, v4i *__restrict__ buf)
+{
+    const int r = tid & 31;
+    const int c = tid >> 5;
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+        const uint32_t word = e == 0 ? w.x : w.y;
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            buf[(2 * c + e) * 64 + 32 * h + r] = expand16((word >> (16 * h)) & 0xffffu);
+    }
+}
+
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train,
+                int nt, int split_rows, uint64_t *__restrict__ partial)
 {
     __shared__ v4i tbuf[2][kTileVec];
-    __shared__ uint4 bbuf[2][kTileRows / 4];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -132,6 +141,14 @@ __global__ __launch_bounds__(kMfmaWaves * 64) __attribute__((amdgpu_waves_per_eu
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int split = blockIdx.y;
     const int qbase = blockIdx.x * kQueriesPerGroup + wave * kQueriesPerWave;
+
+    const int ntiles_all = (nt + kTileRows - 1) / kTileRows;
+    const int tiles_per_split = split_rows / kTileRows;
+    const int t_begin = split * tiles_per_split;
+    const int t_end = min(ntiles_all, t_begin + tiles_per_split);
+
+    uint2 ld = make_uint2(0, 0);
+    if (t_begin < t_end) ld = load_tile(train, nt, t_begin, tid);
 
     // Resident query fragments and query popcounts.
     v4i bq[kQueryBlocks][16];
@@ -144,44 +161,22 @@ __global__ __launch_bounds__(kMfmaWaves * 64) __attribute__((amdgpu_waves_per_eu
         for (int s = 0; s < 16; ++s) {
             const uint32_t w = qn < nq ? query[(size_t)qn * kWords + s] : 0u;
             pc += __popc(w);
-            bq[qb][s] = expand16((w >> (16 * half)) & 0xffffu);
+            bq[qb][s] = expand16_pm1((w >> (16 * half)) & 0xffffu);
         }
         na[qb] = pc;
     }
-
-    const int ntiles_all = (nt + kTileRows - 1) / kTileRows;
-    const int tiles_per_split = split_rows / kTileRows;
-    const int t_begin = split * tiles_per_split;
-    const int t_end = min(ntiles_all, t_begin + tiles_per_split);
 
     uint32_t k1[kQueryBlocks], k2[kQueryBlocks];
 #pragma unroll
     for (int qb = 0; qb < kQueryBlocks; ++qb) k1[qb] = k2[qb] = 0u;
 
-    // Stage the first tile.
-    if (t_begin < t_end) {
-        const v4i *src = reinterpret_cast<const v4i *>(expanded) + (size_t)t_begin * kTileVec;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) tbuf[0][tid + 256 * i] = src[tid + 256 * i];
-        if (tid < kTileRows / 4)
-            bbuf[0][tid] = reinterpret_cast<const uint4 *>(rowbase + (size_t)t_begin * kTileRows)[tid];
-    }
+    if (t_begin < t_end) stage_tile(ld, tid, tbuf[0]);
     __syncthreads();
 
     for (int tile = t_begin; tile < t_end; ++tile) {
         const int buf = (tile - t_begin) & 1;
         const bool more = tile + 1 < t_end;
-
-        // Prefetch the next tile into registers.
-        v4i nx[4];
-        uint4 nb = make_uint4(0, 0, 0, 0);
-        if (more) {
-            const v4i *src = reinterpret_cast<const v4i *>(expanded) + (size_t)(tile + 1) * kTileVec;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) nx[i] = src[tid + 256 * i];
-            if (tid < kTileRows / 4)
-                nb = reinterpret_cast<const uint4 *>(rowbase + (size_t)(tile + 1) * kTileRows)[tid];
-        }
+        if (more) ld = load_tile(train, nt, tile + 1, tid);     // lands during the MFMAs below
 
         v16i acc[kQueryBlocks];
 #pragma unroll
@@ -194,31 +189,39 @@ __global__ __launch_bounds__(kMfmaWaves * 64) __attribute__((amdgpu_waves_per_eu
                 acc[qb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a, bq[qb][s], acc[qb], 0, 0, 0);
         }
 
-        // Epilogue: rows 8 g + 4 half + e, g = 0..3, e = 0..3.
+        // Epilogue.  Register r = 4 g + e holds tile row m = 8 g + 4 half + e,
+        // split-local index tile * 32 - split * split_rows + m.  Padding rows
+        // (past nt, last tile only) have all-zero bytes, so s = 0 there and a
+        // zero key base makes their key 0.
+        const uint32_t kt = (512u << kLocalBits) + kLocalMask -
+                            (uint32_t)(tile * kTileRows - split * split_rows) - 4u * half;
+        const int valid_rows = nt - tile * kTileRows;        // < 32 only in the last tile
+        uint32_t cb[16];
+        if (valid_rows >= kTileRows) {
 #pragma unroll
-        for (int g = 0; g < 4; ++g) {
-            const uint4 bb = bbuf[buf][2 * g + half];
-            const uint32_t base[4] = {bb.x, bb.y, bb.z, bb.w};
+            for (int r = 0; r < 16; ++r) cb[r] = kt - (uint32_t)(8 * (r >> 2) + (r & 3));
+        } else {
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
+            for (int r = 0; r < 16; ++r) {
+                const int m = 8 * (r >> 2) + 4 * half + (r & 3);
+                cb[r] = m < valid_rows ? kt - (uint32_t)(8 * (r >> 2) + (r & 3)) : 0u;
+            }
+        }
 #pragma unroll
-                for (int qb = 0; qb < kQueryBlocks; ++qb) {
-                    const uint32_t key = ((uint32_t)acc[qb][4 * g + e] << 22) + base[e];
-                    k2[qb] = umed3(k1[qb], k2[qb], key);
-                    k1[qb] = max(k1[qb], key);
-                }
+        for (int r = 0; r < 16; ++r) {
+#pragma unroll
+            for (int qb = 0; qb < kQueryBlocks; ++qb) {
+                const uint32_t key = ((uint32_t)acc[qb][r] << kLocalBits) + cb[r];
+                k2[qb] = umed3(k1[qb], k2[qb], key);
+                k1[qb] = max(k1[qb], key);
             }
         }
 
-        if (more) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) tbuf[buf ^ 1][tid + 256 * i] = nx[i];
-            if (tid < kTileRows / 4) bbuf[buf ^ 1][tid] = nb;
-        }
+        if (more) stage_tile(ld, tid, tbuf[buf ^ 1]);
         __syncthreads();
     }
 
-    // Merge the two row halves, decode, store.
+    // Merge the two row halves, decode (d = |a| + 512 - (key >> 21)), store.
 #pragma unroll
     for (int qb = 0; qb < kQueryBlocks; ++qb) {
         const uint32_t o1 = __shfl_xor(k1[qb], 32);
@@ -301,17 +304,20 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= nq) return;
     uint64_t b1 = kNoNeighbour, b2 = kNoNeighbour;
-    for (int s = 0; s < nsplit; ++s) {
-        const uint64_t *src = partial + ((size_t)s * nq + q) * 2;
+    // Eight splits' loads in flight at a time, then a branch-free top-2 update.
+    for (int s0 = 0; s0 < nsplit; s0 += 8) {
+        uint64_t v[16];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            const uint64_t v = src[e];
-            if (v < b1) {
-                b2 = b1;
-                b1 = v;
-            } else if (v < b2) {
-                b2 = v;
-            }
+        for (int i = 0; i < 8; ++i) {
+            const bool in = s0 + i < nsplit;
+            const uint64_t *src = partial + ((size_t)(in ? s0 + i : 0) * nq + q) * 2;
+            v[2 * i] = in ? src[0] : kNoNeighbour;
+            v[2 * i + 1] = in ? src[1] : kNoNeighbour;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            b2 = min(b2, max(b1, v[i]));
+            b1 = min(b1, v[i]);
         }
     }
     const int d1 = b1 == kNoNeighbour ? 513 : (int)(b1 >> 32);
@@ -329,24 +335,12 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(
 
 }  // namespace
 
-hipError_t launch_knn_prep(const uint32_t *train, int64_t nt, const KnnPlan &plan,
-                           uint8_t *expanded, uint32_t *rowbase, hipStream_t stream)
-{
-    const int64_t tiles = (nt + kTileRows - 1) / kTileRows;
-    if (tiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(knn_prep_kernel, dim3((unsigned)tiles), dim3(256), 0, stream, train,
-                       (int)nt, (int)plan.split_rows, reinterpret_cast<uint4 *>(expanded), rowbase);
-    return hipGetLastError();
-}
-
-hipError_t launch_knn_mfma(const uint32_t *query, const uint8_t *expanded,
-                           const uint32_t *rowbase, const KnnPlan &plan, uint64_t *partial,
-                           hipStream_t stream)
+hipError_t launch_knn_mfma(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
+                           uint64_t *partial, hipStream_t stream)
 {
     const int64_t qblocks = (plan.nq + kQueriesPerGroup - 1) / kQueriesPerGroup;
     hipLaunchKernelGGL(knn_mfma_kernel, dim3((unsigned)qblocks, (unsigned)plan.nsplit),
-                       dim3(kMfmaWaves * 64), 0, stream, query, (int)plan.nq,
-                       reinterpret_cast<const uint4 *>(expanded), rowbase, (int)plan.nt,
+                       dim3(kMfmaThreads), 0, stream, query, (int)plan.nq, train, (int)plan.nt,
                        (int)plan.split_rows, partial);
     return hipGetLastError();
 }
@@ -369,7 +363,5 @@ hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k,
                        (int)plan.nq, plan.nsplit, (int)plan.nt, k, ratio, idx, dist, accept);
     return hipGetLastError();
 }
-
-int knn_queries_per_group_mfma() { return kQueriesPerGroup; }
 
 }  // namespace latch

@@ -138,7 +138,10 @@ void release_timed(latch_handle h)
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-KnnPlan plan_knn(int64_t nq, int64_t nt, int path)
+// Train splits: enough (query group, split) workgroups to fill every CU
+// once (two MFMA workgroups or eight popcount workgroups resident per CU),
+// at least 8 tiles (256 rows) per split, split-local indices below 2^21 - 1.
+KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus)
 {
     KnnPlan p;
     p.nq = nq;
@@ -149,17 +152,16 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path)
         p.split_rows = kTileRows;
         return p;
     }
-    const int64_t per_group = path == LATCH_PATH_MFMA ? 256 : 256;
-    const int64_t qgroups = (nq + per_group - 1) / per_group;
-    const int64_t target_groups = path == LATCH_PATH_MFMA ? 1024 : 2048;
-    int64_t nsplit = (target_groups + qgroups - 1) / qgroups;
-    const int64_t max_by_size = (tiles + 7) / 8;              // >= 8 tiles (256 rows) per split
+    const int64_t qgroups = (nq + 255) / 256;
+    const int64_t slots = (int64_t)num_cus * (path == LATCH_PATH_MFMA ? 2 : 8);
+    int64_t nsplit = qgroups >= slots ? 1 : slots / qgroups;
+    const int64_t max_by_size = (tiles + 7) / 8;
     if (nsplit > max_by_size) nsplit = max_by_size;
     if (nsplit < 1) nsplit = 1;
     const int64_t min_by_index = (nt + kMaxSplitRows - 1) / kMaxSplitRows;
     if (nsplit < min_by_index) nsplit = min_by_index;
     if (nsplit > 65535) nsplit = 65535;
-    int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
+    const int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
     p.split_rows = tiles_per_split * kTileRows;
     p.nsplit = (int)((tiles + tiles_per_split - 1) / tiles_per_split);
     return p;
@@ -254,8 +256,12 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.height = height;
     a.width = width;
     a.pitch = pitch;
+    a.table = nullptr;
+    a.image_id = nullptr;
+    a.n_images = 0;
     a.kps = reinterpret_cast<const float4 *>(kps_dev);
     a.n = n_kps;
+    a.n_dev = nullptr;
     a.rot = h->rot_dev;
     a.trip_off = h->trip_off_dev;
     a.desc = desc_dev;
@@ -263,6 +269,36 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.num_cus = h->num_cus;
     hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
+}
+
+int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_images,
+                        const int32_t *image_id_dev, const latch_keypoint *kps_dev, int64_t max_kps,
+                        const int64_t *n_kps_dev, uint32_t *desc_dev, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (max_kps < 0 || max_kps > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "max_kps = %lld out of [0, 2^31)", (long long)max_kps);
+    if (n_images < 0) return fail(h, LATCH_EINVAL, "n_images = %d < 0", n_images);
+    if (max_kps == 0) return LATCH_OK;
+    if (!images_dev || !image_id_dev || !kps_dev || !desc_dev || n_images == 0)
+        return fail(h, LATCH_EINVAL, "null buffer or empty image table");
+    ExtractArgs a;
+    a.img = nullptr;
+    a.height = a.width = a.pitch = 0;
+    a.table = reinterpret_cast<const ImageEntry *>(images_dev);
+    a.image_id = image_id_dev;
+    a.n_images = n_images;
+    a.kps = reinterpret_cast<const float4 *>(kps_dev);
+    a.n = max_kps;
+    a.n_dev = n_kps_dev;
+    a.rot = h->rot_dev;
+    a.trip_off = h->trip_off_dev;
+    a.desc = desc_dev;
+    a.flags = h->flags_dev;
+    a.num_cus = h->num_cus;
+    hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
 }
 
 int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32_t *train_dev,
@@ -284,28 +320,16 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
         return fail(h, LATCH_EINVAL, "null buffer");
     if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
 
-    const KnnPlan plan = plan_knn(nq, nt, path);
-    const int64_t tiles = (nt + kTileRows - 1) / kTileRows;
+    const KnnPlan plan = plan_knn(nq, nt, path, h->num_cus);
     const size_t partial_bytes = align_up((size_t)plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
-    size_t expanded_bytes = 0, rowbase_bytes = 0;
-    if (path == LATCH_PATH_MFMA) {
-        expanded_bytes = (size_t)tiles * kTileBytes;
-        rowbase_bytes = align_up((size_t)tiles * kTileRows * sizeof(uint32_t), 256);
-    }
-    int rc = ensure_workspace(h, partial_bytes + expanded_bytes + rowbase_bytes);
+    int rc = ensure_workspace(h, partial_bytes);
     if (rc != LATCH_OK) return rc;
     uint64_t *partial = reinterpret_cast<uint64_t *>(h->ws);
-    uint8_t *expanded = h->ws + partial_bytes;
-    uint32_t *rowbase = reinterpret_cast<uint32_t *>(h->ws + partial_bytes + expanded_bytes);
 
     hipError_t e;
     if (path == LATCH_PATH_MFMA) {
-        e = timed_launch(h, "knn_prep", stream, [&] {
-            return launch_knn_prep(train_dev, nt, plan, expanded, rowbase, stream);
-        });
-        if (e != hipSuccess) return hip_fail(h, e, "prep launch");
         e = timed_launch(h, "knn_mfma", stream, [&] {
-            return launch_knn_mfma(query_dev, expanded, rowbase, plan, partial, stream);
+            return launch_knn_mfma(query_dev, train_dev, plan, partial, stream);
         });
         if (e != hipSuccess) return hip_fail(h, e, "mfma launch");
     } else {
