@@ -68,6 +68,21 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_mib": mib, "bytes": mib << 20}), flush=True)
 
 
+def recorded_traffic(kernel):
+    """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in
+    profiles/traffic.json for this kernel, or None when missing or when the
+    kernel's source has changed since the counters were taken."""
+    import hashlib
+    try:
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"][kernel]
+        src = open(os.path.join(ROOT, rec["source"]), "rb").read()
+    except (OSError, KeyError, ValueError):
+        return None
+    if hashlib.sha256(src).hexdigest() != rec["source_sha256"]:
+        return None
+    return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
 def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p))
 
@@ -183,6 +198,9 @@ def main():
         achieved = pairs * 32 / (kd["avg_ms"] * 1e-3) / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak,
                 "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
+
+    roof["traffic"] = recorded_traffic(dom)
+    roof["traffic_unit"] = "bytes/launch"
 
     # --- CPU oracle baseline: whole steps on the host cores. ---
     cpu = None
