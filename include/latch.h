@@ -84,6 +84,7 @@ typedef enum {
 /* Bits of the sticky device error word. */
 #define LATCH_FLAG_BAD_KEYPOINT 1u  /* a keypoint outside the resampling rule's domain; its descriptor is all zero */
 #define LATCH_FLAG_BAD_IMAGE 2u     /* batched extraction: image id out of range or malformed image entry */
+#define LATCH_FLAG_BAD_PAIR 4u      /* batched matching: a pair outside its arrays (skipped, outputs untouched) */
 
 /* One image of a batched extraction (device memory), 24 bytes. */
 typedef struct {
@@ -165,6 +166,36 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
                 int32_t *idx_dev, int32_t *dist_dev, uint8_t *accept_dev, int path,
                 hipStream_t stream);
 
+/* One pair of a batched matching (device memory), 40 bytes. */
+typedef struct {
+    int64_t query_first;  /* first row of this pair's queries in query_dev */
+    int64_t nq;           /* query rows, >= 0 */
+    int64_t train_first;  /* first row of its train descriptors in train_dev */
+    int64_t nt;           /* train rows, in [0, 2^21 - 32] */
+    int64_t out_first;    /* first output row in idx/dist (rows of k) and accept */
+} latch_pair;
+
+/*
+ * Batched brute-force 2-NN: many (query range, train range) pairs in one
+ * persistent launch, e.g. the consecutive image pairs of an SfM batch
+ * (Sec. 4-5: matching dominates the pipeline's run time).  Each pair gives
+ * exactly what hamming_knn gives for its ranges, with train indices relative
+ * to train_first, written to output rows out_first .. out_first + nq - 1.
+ *   query_dev: uint32[query_rows][16]; train_dev: uint32[train_rows][16]
+ *              (the same array may serve as both).
+ *   pairs_dev: latch_pair[n_pairs], device memory (the caller's work list;
+ *              contents may change between replays of a captured graph).
+ *   idx_dev, dist_dev: int32[out_rows][k]; accept_dev: uint8[out_rows] or NULL.
+ * A pair whose ranges fall outside query_rows / train_rows / out_rows, or
+ * with nt > 2^21 - 32, is skipped and sets LATCH_FLAG_BAD_PAIR.  Pairs'
+ * output ranges should not overlap (they are written concurrently).  k,
+ * ratio and path as for hamming_knn.  May grow the handle's workspace.
+ */
+int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_rows,
+                      const uint32_t *train_dev, int64_t train_rows, const latch_pair *pairs_dev,
+                      int n_pairs, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                      uint8_t *accept_dev, int64_t out_rows, int path, hipStream_t stream);
+
 /*
  * Read the sticky device error word (LATCH_FLAG_* bits) after all work
  * enqueued on `stream` so far; synchronises that stream.  If clear != 0 the
@@ -189,9 +220,10 @@ int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
  * kernel the handle launches is bracketed by two hipEventRecord calls on the
  * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops
  * recording).  latch_timing_read waits for the recorded events and returns,
- * for one kernel name ("extract", "knn_prep", "knn_mfma", "knn_popcount",
- * "knn_merge"), the number of launches recorded and their summed duration in
- * milliseconds.  Not for use under stream capture.
+ * for one kernel name ("extract", "knn_mfma", "knn_popcount", "knn_merge",
+ * "knn_batch_mfma", "knn_batch_popcount"; the batch names cover the whole
+ * batched sequence), the number of launches recorded and their summed
+ * duration in milliseconds.  Not for use under stream capture.
  */
 int latch_timing_enable(latch_handle h, int enable);
 int latch_timing_read(latch_handle h, const char *kernel, int *launches, double *total_ms);

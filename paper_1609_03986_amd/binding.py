@@ -25,13 +25,14 @@ LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE = 0, -1, -2, -
 PATHS = {"auto": 0, "mfma": 1, "popcount": 2}
 FLAG_BAD_KEYPOINT = 1
 FLAG_BAD_IMAGE = 2
+FLAG_BAD_PAIR = 4
 NO_NEIGHBOUR_DIST = 513
 STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATCH_EDEVICE",
                 -4: "LATCH_ERANGE"}
 
 # Every symbol include/latch.h declares.
 EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "hamming_knn",
-           "latch_check_errors",
+           "hamming_knn_batch", "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
 KERNELS = ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge")
@@ -64,6 +65,8 @@ def load_library():
     lib.latch_extract_batch.argtypes = [P, P, I, P, P, I64, P, P, P]
     lib.latch_extract_batch.restype = I
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
+    lib.hamming_knn_batch.argtypes = [P, P, I64, P, I64, P, I, I, F, P, P, P, I64, I, P]
+    lib.hamming_knn_batch.restype = I
     lib.hamming_knn.restype = I
     lib.latch_check_errors.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32), I]
     lib.latch_check_errors.restype = I
@@ -218,6 +221,38 @@ def hamming_knn(h, query, train, k=2, ratio=0.8, path="auto", idx=None, dist=Non
     return idx, dist, accept
 
 
+def pair_table(pairs, device="cuda"):
+    """latch_pair table from rows (query_first, nq, train_first, nt, out_first):
+    an int64 CUDA tensor [n, 5]."""
+    import torch
+    arr = np.asarray(pairs, np.int64).reshape(-1, 5)
+    return torch.from_numpy(np.ascontiguousarray(arr)).to(device)
+
+
+def hamming_knn_batch(h, query, train, pairs, out_rows, k=2, ratio=0.8, path="auto", idx=None,
+                      dist=None, accept=None, want_accept=True, stream=None):
+    """Batched k-NN over a pair table (see pair_table).  Returns (idx, dist, accept)
+    with out_rows rows; rows no pair writes are left as allocated."""
+    import torch
+    dev = query.device
+    if idx is None:
+        idx = torch.full((out_rows, k), -2, dtype=torch.int32, device=dev)
+    if dist is None:
+        dist = torch.full((out_rows, k), -2, dtype=torch.int32, device=dev)
+    if accept is None and want_accept:
+        accept = torch.full((out_rows,), 255, dtype=torch.uint8, device=dev)
+    acc_ptr = _dev(accept, torch.uint8, "accept") if accept is not None else None
+    qptr = _dev(query, torch.int32, "query") if query.shape[0] else None
+    tptr = _dev(train, torch.int32, "train") if train.shape[0] else None
+    rc = load_library().hamming_knn_batch(h, qptr, query.shape[0], tptr, train.shape[0],
+                                          _dev(pairs, torch.int64, "pairs"), pairs.shape[0],
+                                          int(k), float(ratio), _dev(idx, torch.int32, "idx"),
+                                          _dev(dist, torch.int32, "dist"), acc_ptr, int(out_rows),
+                                          PATHS[path], _stream_ptr(stream))
+    _check(h, rc)
+    return idx, dist, accept
+
+
 def latch_check_errors(h, stream=None, clear=True):
     v = ctypes.c_uint32()
     rc = load_library().latch_check_errors(h, _stream_ptr(stream), ctypes.byref(v), int(clear))
@@ -252,6 +287,9 @@ class Latch:
 
     def knn(self, query, train, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn(self.h, query, train, k, ratio, path, **kw)
+
+    def knn_batch(self, query, train, pairs, out_rows, k=2, ratio=0.8, path="auto", **kw):
+        return hamming_knn_batch(self.h, query, train, pairs, out_rows, k, ratio, path, **kw)
 
     def check_errors(self, stream=None, clear=True):
         return latch_check_errors(self.h, stream, clear)

@@ -34,6 +34,8 @@ constexpr uint64_t kNoNeighbour = ~0ull;         // partial-result sentinel
 // Sticky error-word bits (same values as the LATCH_FLAG_* of the C ABI).
 constexpr uint32_t kFlagBadKeypoint = 1u;
 constexpr uint32_t kFlagBadImage = 2u;
+constexpr uint32_t kFlagBadPair = 4u;
+constexpr int64_t kMaxRows = 2147483647LL;
 
 // Layout-compatible with latch_image of the C ABI.
 struct ImageEntry {
@@ -70,6 +72,44 @@ hipError_t launch_knn_mfma(const uint32_t *query, const uint32_t *train, const K
                            uint64_t *partial, hipStream_t stream);
 hipError_t launch_knn_popcount(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
                                uint64_t *partial, hipStream_t stream);
+// Layout-compatible with latch_pair of the C ABI.
+struct PairEntry {
+    int64_t query_first, nq, train_first, nt, out_first;
+};
+static_assert(sizeof(PairEntry) == 40, "latch_pair layout");
+
+struct PairInfo {            // per pair, computed on the device
+    int64_t item_first;
+    int32_t qgroups;
+    int32_t valid;
+};
+
+struct BatchState {          // batch header in the workspace
+    int64_t items;
+    uint32_t next_item;      // atomic work counter, reset by the setup kernel
+    uint32_t pad;
+};
+
+struct BatchArgs {
+    const uint32_t *query, *train;
+    int64_t query_rows, train_rows, out_rows;
+    const PairEntry *pairs;
+    int n_pairs;
+    int64_t item_capacity;
+    PairInfo *info;
+    BatchState *state;
+    int32_t *item_pair;
+    int k;
+    float ratio;
+    int32_t *idx, *dist;
+    uint8_t *accept;
+    uint32_t *flags;
+    int num_cus;
+    bool mfma;
+};
+
+hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream);
+
 hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k, float ratio,
                             int32_t *idx, int32_t *dist, uint8_t *accept, hipStream_t stream);
 

@@ -129,18 +129,60 @@ __device__ __forceinline__ void stage_tile(uint2 w, int tid, v4i *__restrict__ b
     }
 }
 
-__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
-knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train,
-                int nt, int split_rows, uint64_t *__restrict__ partial)
-{
-    __shared__ v4i tbuf[2][kTileVec];
+// Where a work item's results go: per-(split, query) partials for a later
+// merge, or (one split only) the final idx / dist / accept rows directly.
+struct ItemOut {
+    uint64_t *partial;      // partial + (split * nq + q) * 2, or nullptr for direct
+    int32_t *idx;           // direct: rows q of this item's query range
+    int32_t *dist;
+    uint8_t *accept;
+    int k;
+    float ratio;
+};
 
+// Final results of one query from its two best packed (distance << 32 | index).
+__device__ __forceinline__ void store_final(uint64_t b1, uint64_t b2, int nt, const ItemOut &o,
+                                            int q)
+{
+    const int d1 = b1 == kNoNeighbour ? 513 : (int)(b1 >> 32);
+    const int d2 = b2 == kNoNeighbour ? 513 : (int)(b2 >> 32);
+    const int j1 = b1 == kNoNeighbour ? -1 : (int)(uint32_t)b1;
+    const int j2 = b2 == kNoNeighbour ? -1 : (int)(uint32_t)b2;
+    o.idx[(size_t)q * o.k] = j1;
+    o.dist[(size_t)q * o.k] = d1;
+    if (o.k == 2) {
+        o.idx[(size_t)q * o.k + 1] = j2;
+        o.dist[(size_t)q * o.k + 1] = d2;
+    }
+    if (o.accept) o.accept[q] = (uint8_t)(nt >= 2 && (double)d1 < (double)o.ratio * (double)d2);
+}
+
+__device__ __forceinline__ void store_pair(uint64_t b1, uint64_t b2, int nq, int nt, int split,
+                                           const ItemOut &o, int q)
+{
+    if (o.partial) {
+        uint64_t *dst = o.partial + ((size_t)split * nq + q) * 2;
+        dst[0] = b1;
+        dst[1] = b2;
+    } else {
+        store_final(b1, b2, nt, o, q);
+    }
+}
+
+// One work item of the MFMA matcher: queries qgroup * 256 .. + 255 of
+// `query` (nq rows) against train rows split * split_rows .. + split_rows - 1
+// of `train` (nt rows).  All 256 threads of the workgroup take part; tbuf is
+// the workgroup's 2 x 16 KB LDS staging buffer.
+__device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, int nq,
+                                          const uint32_t *__restrict__ train, int nt, int qgroup,
+                                          int split, int split_rows, const ItemOut &out,
+                                          v4i (*tbuf)[kTileVec])
+{
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int half = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int split = blockIdx.y;
-    const int qbase = blockIdx.x * kQueriesPerGroup + wave * kQueriesPerWave;
+    const int qbase = qgroup * kQueriesPerGroup + wave * kQueriesPerWave;
 
     const int ntiles_all = (nt + kTileRows - 1) / kTileRows;
     const int tiles_per_split = split_rows / kTileRows;
@@ -170,6 +212,7 @@ knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__re
 #pragma unroll
     for (int qb = 0; qb < kQueryBlocks; ++qb) k1[qb] = k2[qb] = 0u;
 
+    __syncthreads();       // the staging buffer may still be read by a previous item
     if (t_begin < t_end) stage_tile(ld, tid, tbuf[0]);
     __syncthreads();
 
@@ -244,23 +287,30 @@ knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__re
                     r[e] = ((uint64_t)d << 32) | j;
                 }
             }
-            uint64_t *dst = partial + ((size_t)split * nq + qn) * 2;
-            dst[0] = r[0];
-            dst[1] = r[1];
+            store_pair(r[0], r[1], nq, nt, split, out, qn);
         }
     }
+}
+
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train,
+                int nt, int split_rows, uint64_t *__restrict__ partial)
+{
+    __shared__ v4i tbuf[2][kTileVec];
+    const ItemOut out{partial, nullptr, nullptr, nullptr, 2, 0.f};
+    mfma_item(query, nq, train, nt, blockIdx.x, blockIdx.y, split_rows, out, tbuf);
 }
 
 // ---------------------------------------------------------------------------
 // Popcount matcher.  One query per lane; grid (query blocks of 256, splits).
 // key = (d << 21) | jl with d <= 512, jl < 2^21 - 1, so ~0u means "none".
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void knn_popcount_kernel(
-    const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train, int nt,
-    int split_rows, uint64_t *__restrict__ partial)
+__device__ __forceinline__ void popcount_item(const uint32_t *__restrict__ query, int nq,
+                                              const uint32_t *__restrict__ train, int nt,
+                                              int qgroup, int split, int split_rows,
+                                              const ItemOut &out)
 {
-    const int qn = blockIdx.x * 256 + threadIdx.x;
-    const int split = blockIdx.y;
+    const int qn = qgroup * 256 + threadIdx.x;
     const int j0 = split * split_rows;
     const int j1 = min(nt, j0 + split_rows);
 
@@ -282,14 +332,22 @@ __global__ __launch_bounds__(256) void knn_popcount_kernel(
 
     if (qn < nq) {
         const uint32_t kk[2] = {k1, k2};
-        uint64_t *dst = partial + ((size_t)split * nq + qn) * 2;
+        uint64_t r[2];
 #pragma unroll
-        for (int e = 0; e < 2; ++e) {
-            dst[e] = kk[e] == ~0u ? kNoNeighbour
-                                  : (((uint64_t)(kk[e] >> kLocalBits) << 32) |
-                                     (uint32_t)(j0 + (int)(kk[e] & kLocalMask)));
-        }
+        for (int e = 0; e < 2; ++e)
+            r[e] = kk[e] == ~0u ? kNoNeighbour
+                                : (((uint64_t)(kk[e] >> kLocalBits) << 32) |
+                                   (uint32_t)(j0 + (int)(kk[e] & kLocalMask)));
+        store_pair(r[0], r[1], nq, nt, split, out, qn);
     }
+}
+
+__global__ __launch_bounds__(256) void knn_popcount_kernel(
+    const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train, int nt,
+    int split_rows, uint64_t *__restrict__ partial)
+{
+    const ItemOut out{partial, nullptr, nullptr, nullptr, 2, 0.f};
+    popcount_item(query, nq, train, nt, blockIdx.x, blockIdx.y, split_rows, out);
 }
 
 // ---------------------------------------------------------------------------
@@ -320,17 +378,148 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(
             b1 = min(b1, v[i]);
         }
     }
-    const int d1 = b1 == kNoNeighbour ? 513 : (int)(b1 >> 32);
-    const int d2 = b2 == kNoNeighbour ? 513 : (int)(b2 >> 32);
-    const int j1 = b1 == kNoNeighbour ? -1 : (int)(uint32_t)b1;
-    const int j2 = b2 == kNoNeighbour ? -1 : (int)(uint32_t)b2;
-    idx[(size_t)q * k] = j1;
-    dist[(size_t)q * k] = d1;
-    if (k == 2) {
-        idx[(size_t)q * k + 1] = j2;
-        dist[(size_t)q * k + 1] = d2;
+    const ItemOut out{nullptr, idx, dist, accept, k, ratio};
+    store_final(b1, b2, nt, out, q);
+}
+
+// ---------------------------------------------------------------------------
+// Batched matching: many (query range, train range, output range) pairs in
+// one persistent launch.  Work item = (pair, 256-query group) over the pair's
+// whole train range, so results are final and go straight to the outputs.
+// A one-block setup kernel validates the pairs, scans their item counts and
+// resets the atomic work counter (so the sequence is replayable from a HIP
+// graph without memset nodes); a fill kernel writes the item -> pair map;
+// persistent workgroups then claim items through the counter.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void knn_batch_setup_kernel(
+    const PairEntry *__restrict__ pairs, int n_pairs, int64_t query_rows, int64_t train_rows,
+    int64_t out_rows, int64_t item_capacity, PairInfo *__restrict__ info,
+    BatchState *__restrict__ st, uint32_t *__restrict__ flags)
+{
+    __shared__ int64_t part[256];
+    const int tid = threadIdx.x;
+    const int chunk = (n_pairs + 255) / 256;
+    const int p0 = min(n_pairs, tid * chunk), p1 = min(n_pairs, p0 + chunk);
+    int64_t local = 0;
+    bool bad = false;
+    for (int p = p0; p < p1; ++p) {
+        const PairEntry e = pairs[p];
+        const bool ok = e.nq >= 0 && e.nt >= 0 && e.nq <= kMaxRows && e.nt <= kMaxSplitRows &&
+                        e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
+                        (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
+                        e.out_first >= 0 && e.out_first + e.nq <= out_rows;
+        bad |= !ok;
+        local += ok ? (e.nq + 255) / 256 : 0;
     }
-    if (accept) accept[q] = (uint8_t)(nt >= 2 && (double)d1 < (double)ratio * (double)d2);
+    part[tid] = local;
+    __syncthreads();
+    // Inclusive scan of the 256 chunk sums (Hillis-Steele).
+    for (int off = 1; off < 256; off <<= 1) {
+        const int64_t v = tid >= off ? part[tid - off] : 0;
+        __syncthreads();
+        part[tid] += v;
+        __syncthreads();
+    }
+    // The item map holds item_capacity entries, enough for every batch whose
+    // pairs' output ranges do not overlap; a batch that needs more is not run.
+    const bool overflow = part[255] > item_capacity;
+    int64_t first = part[tid] - local;
+    for (int p = p0; p < p1; ++p) {
+        const PairEntry e = pairs[p];
+        const bool ok = e.nq >= 0 && e.nt >= 0 && e.nq <= kMaxRows && e.nt <= kMaxSplitRows &&
+                        e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
+                        (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
+                        e.out_first >= 0 && e.out_first + e.nq <= out_rows;
+        const int64_t groups = ok && !overflow ? (e.nq + 255) / 256 : 0;
+        info[p].item_first = first;
+        info[p].qgroups = (int32_t)groups;
+        info[p].valid = ok && !overflow;
+        first += groups;
+    }
+    if (bad || overflow) atomicOr(flags, kFlagBadPair);
+    if (tid == 255) {
+        st->items = overflow ? 0 : part[255];
+        st->next_item = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void knn_batch_fill_kernel(const PairInfo *__restrict__ info,
+                                                             int n_pairs,
+                                                             int32_t *__restrict__ item_pair)
+{
+    for (int p = blockIdx.x; p < n_pairs; p += gridDim.x) {
+        const PairInfo pi = info[p];
+        for (int i = threadIdx.x; i < pi.qgroups; i += 256) item_pair[pi.item_first + i] = p;
+    }
+}
+
+// Claims the next work item for the whole workgroup; -1 when none is left.
+__device__ __forceinline__ int64_t claim_item(BatchState *__restrict__ st, int *slot)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t it = atomicAdd(&st->next_item, 1u);
+        *slot = (int64_t)it < st->items ? (int)it : -1;
+    }
+    __syncthreads();
+    const int it = *slot;
+    __syncthreads();
+    return it;
+}
+
+template <bool kMfma>
+__device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
+                                           const uint32_t *__restrict__ train,
+                                           const PairEntry *__restrict__ pairs,
+                                           const PairInfo *__restrict__ info,
+                                           const int32_t *__restrict__ item_pair,
+                                           BatchState *__restrict__ st, int k, float ratio,
+                                           int32_t *__restrict__ idx, int32_t *__restrict__ dist,
+                                           uint8_t *__restrict__ accept, v4i (*tbuf)[kTileVec],
+                                           int *slot, int n_pairs)
+{
+    for (;;) {
+        const int item = claim_item(st, slot);
+        if (item < 0) break;
+        const int p = item_pair[item];
+        if (p < 0 || p >= n_pairs) continue;     // cannot happen for a map written by the fill kernel
+        const PairEntry e = pairs[p];
+        const int qgroup = (int)(item - info[p].item_first);
+        const int nt = (int)e.nt;
+        const int split_rows = max(kTileRows, (nt + kTileRows - 1) / kTileRows * kTileRows);
+        const ItemOut out{nullptr, idx + e.out_first * k, dist + e.out_first * k,
+                          accept ? accept + e.out_first : nullptr, k, ratio};
+        const uint32_t *q = query + (size_t)e.query_first * kWords;
+        const uint32_t *t = train + (size_t)(nt ? e.train_first : 0) * kWords;
+        if constexpr (kMfma)
+            mfma_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out, tbuf);
+        else
+            popcount_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out);
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_batch_mfma_kernel(const uint32_t *__restrict__ query, const uint32_t *__restrict__ train,
+                      const PairEntry *__restrict__ pairs, int n_pairs,
+                      const PairInfo *__restrict__ info,
+                      const int32_t *__restrict__ item_pair, BatchState *__restrict__ st, int k,
+                      float ratio, int32_t *__restrict__ idx, int32_t *__restrict__ dist,
+                      uint8_t *__restrict__ accept)
+{
+    __shared__ v4i tbuf[2][kTileVec];
+    __shared__ int slot;
+    batch_loop<true>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist, accept, tbuf,
+                     &slot, n_pairs);
+}
+
+__global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
+    const uint32_t *__restrict__ query, const uint32_t *__restrict__ train,
+    const PairEntry *__restrict__ pairs, int n_pairs, const PairInfo *__restrict__ info,
+    const int32_t *__restrict__ item_pair, BatchState *__restrict__ st, int k, float ratio,
+    int32_t *__restrict__ idx, int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
+{
+    __shared__ int slot;
+    batch_loop<false>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist, accept,
+                      nullptr, &slot, n_pairs);
 }
 
 }  // namespace
@@ -361,6 +550,29 @@ hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k,
     const int64_t blocks = (plan.nq + 255) / 256;
     hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, partial,
                        (int)plan.nq, plan.nsplit, (int)plan.nt, k, ratio, idx, dist, accept);
+    return hipGetLastError();
+}
+
+hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream)
+{
+    hipLaunchKernelGGL(knn_batch_setup_kernel, dim3(1), dim3(256), 0, stream, a.pairs, a.n_pairs,
+                       a.query_rows, a.train_rows, a.out_rows, a.item_capacity, a.info, a.state,
+                       a.flags);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int fill_blocks = a.n_pairs < 4096 ? a.n_pairs : 4096;
+    hipLaunchKernelGGL(knn_batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a.info,
+                       a.n_pairs, a.item_pair);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int blocks = a.num_cus * (a.mfma ? 2 : 8);
+    if (a.mfma)
+        hipLaunchKernelGGL(knn_batch_mfma_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
+                           a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
+                           a.idx, a.dist, a.accept);
+    else
+        hipLaunchKernelGGL(knn_batch_popcount_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
+                           a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
+                           a.idx, a.dist, a.accept);
     return hipGetLastError();
 }
 

@@ -376,6 +376,58 @@ int latch_timing_read(latch_handle h, const char *kernel, int *launches, double 
     return LATCH_OK;
 }
 
+int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_rows,
+                      const uint32_t *train_dev, int64_t train_rows, const latch_pair *pairs_dev,
+                      int n_pairs, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                      uint8_t *accept_dev, int64_t out_rows, int path, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (n_pairs < 0 || query_rows < 0 || train_rows < 0 || out_rows < 0 ||
+        query_rows > LATCH_MAX_ROWS || train_rows > LATCH_MAX_ROWS || out_rows > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "negative or too large batch size");
+    if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
+    if (!(ratio > 0.0f && ratio <= 1.0f))
+        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
+    if (path != LATCH_PATH_AUTO && path != LATCH_PATH_MFMA && path != LATCH_PATH_POPCOUNT)
+        return fail(h, LATCH_EINVAL, "unknown path %d", path);
+    if (n_pairs == 0) return LATCH_OK;
+    if (!pairs_dev || !idx_dev || !dist_dev || (query_rows > 0 && !query_dev) ||
+        (train_rows > 0 && !train_dev))
+        return fail(h, LATCH_EINVAL, "null buffer");
+    if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
+
+    const int64_t item_capacity = out_rows / 256 + n_pairs + 1;
+    const size_t info_bytes = align_up((size_t)n_pairs * sizeof(PairInfo), 256);
+    const size_t state_bytes = 256;
+    const size_t map_bytes = align_up((size_t)item_capacity * sizeof(int32_t), 256);
+    int rc = ensure_workspace(h, info_bytes + state_bytes + map_bytes);
+    if (rc != LATCH_OK) return rc;
+    BatchArgs a;
+    a.query = query_dev;
+    a.train = train_dev;
+    a.query_rows = query_rows;
+    a.train_rows = train_rows;
+    a.out_rows = out_rows;
+    a.pairs = reinterpret_cast<const PairEntry *>(pairs_dev);
+    a.n_pairs = n_pairs;
+    a.item_capacity = item_capacity;
+    a.info = reinterpret_cast<PairInfo *>(h->ws);
+    a.state = reinterpret_cast<BatchState *>(h->ws + info_bytes);
+    a.item_pair = reinterpret_cast<int32_t *>(h->ws + info_bytes + state_bytes);
+    a.k = k;
+    a.ratio = ratio;
+    a.idx = idx_dev;
+    a.dist = dist_dev;
+    a.accept = accept_dev;
+    a.flags = h->flags_dev;
+    a.num_cus = h->num_cus;
+    a.mfma = path == LATCH_PATH_MFMA;
+    hipError_t e = timed_launch(h, a.mfma ? "knn_batch_mfma" : "knn_batch_popcount", stream,
+                                [&] { return launch_knn_batch(a, stream); });
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched knn launch");
+}
+
 int latch_check_errors(latch_handle h, hipStream_t stream, uint32_t *flags_out, int clear)
 {
     if (!h || !flags_out) return LATCH_EINVAL;
