@@ -197,6 +197,49 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
                       uint8_t *accept_dev, int64_t out_rows, int path, hipStream_t stream);
 
 /*
+ * Plans: one batched extract + match sequence captured once as a HIP graph
+ * and replayed with a single graph launch.  The plan fixes the device
+ * buffers below (pointers), not their contents: between runs the caller may
+ * rewrite the image table, keypoints, image ids, keypoint count and pairs.
+ * Each run extracts descriptors for the batch's keypoints into `desc` (as
+ * latch_extract_batch) and then matches the pairs, whose query and train
+ * rows both index `desc` (as hamming_knn_batch).
+ */
+typedef struct latch_plan_ctx *latch_plan;
+
+typedef struct {
+    const latch_image *images;     /* [n_images] */
+    int32_t n_images;
+    const int32_t *image_id;       /* [max_kps] */
+    const latch_keypoint *kps;     /* [max_kps] */
+    const int64_t *n_kps;          /* device count to process (<= max_kps), or NULL for max_kps */
+    int64_t max_kps;
+    uint32_t *desc;                /* [max_kps][16] */
+    const latch_pair *pairs;       /* [n_pairs]; ranges index desc rows */
+    int32_t n_pairs;
+    int32_t k;                     /* 1 or 2 */
+    float ratio;                   /* (0, 1] */
+    int32_t path;                  /* latch_path */
+    int32_t *idx, *dist;           /* [out_rows][k] */
+    uint8_t *accept;               /* [out_rows] or NULL */
+    int64_t out_rows;
+} latch_plan_desc;
+
+/*
+ * Capture a plan.  Validates the host-checkable fields as the two batched
+ * calls do, allocates the plan's own workspace (device memory it owns until
+ * latch_plan_destroy) and captures the graph on a private stream.  The plan
+ * uses the handle's tables and error word: destroy plans before their handle.
+ */
+int latch_plan_create(latch_handle h, const latch_plan_desc *desc, latch_plan *out);
+
+/* One replay of the plan's graph on `stream` (asynchronous, like every call). */
+int latch_plan_run(latch_plan p, hipStream_t stream);
+
+/* Release a plan (synchronises the device first).  NULL is a no-op. */
+void latch_plan_destroy(latch_plan p);
+
+/*
  * Read the sticky device error word (LATCH_FLAG_* bits) after all work
  * enqueued on `stream` so far; synchronises that stream.  If clear != 0 the
  * word is reset to zero afterwards.

@@ -32,7 +32,8 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
 
 # Every symbol include/latch.h declares.
 EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "hamming_knn",
-           "hamming_knn_batch", "latch_check_errors",
+           "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
+           "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
 KERNELS = ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge")
@@ -67,6 +68,12 @@ def load_library():
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
     lib.hamming_knn_batch.argtypes = [P, P, I64, P, I64, P, I, I, F, P, P, P, I64, I, P]
     lib.hamming_knn_batch.restype = I
+    lib.latch_plan_create.argtypes = [P, P, ctypes.POINTER(P)]
+    lib.latch_plan_create.restype = I
+    lib.latch_plan_run.argtypes = [P, P]
+    lib.latch_plan_run.restype = I
+    lib.latch_plan_destroy.argtypes = [P]
+    lib.latch_plan_destroy.restype = None
     lib.hamming_knn.restype = I
     lib.latch_check_errors.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32), I]
     lib.latch_check_errors.restype = I
@@ -253,6 +260,58 @@ def hamming_knn_batch(h, query, train, pairs, out_rows, k=2, ratio=0.8, path="au
     return idx, dist, accept
 
 
+class _PlanDesc(ctypes.Structure):
+    _fields_ = [("images", ctypes.c_void_p), ("n_images", ctypes.c_int32),
+                ("image_id", ctypes.c_void_p), ("kps", ctypes.c_void_p),
+                ("n_kps", ctypes.c_void_p), ("max_kps", ctypes.c_int64),
+                ("desc", ctypes.c_void_p), ("pairs", ctypes.c_void_p),
+                ("n_pairs", ctypes.c_int32), ("k", ctypes.c_int32), ("ratio", ctypes.c_float),
+                ("path", ctypes.c_int32), ("idx", ctypes.c_void_p), ("dist", ctypes.c_void_p),
+                ("accept", ctypes.c_void_p), ("out_rows", ctypes.c_int64)]
+
+
+class Plan:
+    """A captured batched extract + match graph (latch_plan_*).  Holds references
+    to the device tensors whose pointers the graph uses."""
+
+    def __init__(self, h, table, n_images, image_id, kps, desc, pairs, idx, dist, accept=None,
+                 n_kps=None, k=2, ratio=0.8, path="auto"):
+        import torch
+        self._keep = (table, image_id, kps, desc, pairs, idx, dist, accept, n_kps)
+        d = _PlanDesc()
+        d.images = _dev(table, torch.uint8, "table").value
+        d.n_images = n_images
+        d.image_id = _dev(image_id, torch.int32, "image_id").value
+        d.kps = _dev(kps, torch.float32, "kps").value
+        d.n_kps = _dev(n_kps, torch.int64, "n_kps").value if n_kps is not None else None
+        d.max_kps = kps.shape[0]
+        d.desc = _dev(desc, torch.int32, "desc").value
+        d.pairs = _dev(pairs, torch.int64, "pairs").value
+        d.n_pairs = pairs.shape[0]
+        d.k, d.ratio, d.path = k, float(ratio), PATHS[path]
+        d.idx = _dev(idx, torch.int32, "idx").value
+        d.dist = _dev(dist, torch.int32, "dist").value
+        d.accept = _dev(accept, torch.uint8, "accept").value if accept is not None else None
+        d.out_rows = idx.shape[0]
+        self.h = h
+        self.p = ctypes.c_void_p()
+        _check(h, load_library().latch_plan_create(h, ctypes.byref(d), ctypes.byref(self.p)))
+
+    def run(self, stream=None):
+        _check(self.h, load_library().latch_plan_run(self.p, _stream_ptr(stream)))
+
+    def close(self):
+        if self.p:
+            load_library().latch_plan_destroy(self.p)
+            self.p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def latch_check_errors(h, stream=None, clear=True):
     v = ctypes.c_uint32()
     rc = load_library().latch_check_errors(h, _stream_ptr(stream), ctypes.byref(v), int(clear))
@@ -290,6 +349,9 @@ class Latch:
 
     def knn_batch(self, query, train, pairs, out_rows, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn_batch(self.h, query, train, pairs, out_rows, k, ratio, path, **kw)
+
+    def plan(self, *args, **kw):
+        return Plan(self.h, *args, **kw)
 
     def check_errors(self, stream=None, clear=True):
         return latch_check_errors(self.h, stream, clear)

@@ -167,7 +167,73 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus)
     return p;
 }
 
+size_t batch_workspace_bytes(int n_pairs, int64_t out_rows)
+{
+    const int64_t item_capacity = out_rows / 256 + n_pairs + 1;
+    return align_up((size_t)n_pairs * sizeof(PairInfo), 256) + 256 +
+           align_up((size_t)item_capacity * sizeof(int32_t), 256);
+}
+
+// Arguments of the batched matcher with its workspace at `ws`
+// (batch_workspace_bytes bytes).
+BatchArgs batch_args(latch_handle h, uint8_t *ws, const uint32_t *query_dev, int64_t query_rows,
+                     const uint32_t *train_dev, int64_t train_rows, const latch_pair *pairs_dev,
+                     int n_pairs, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                     uint8_t *accept_dev, int64_t out_rows, int path)
+{
+    const size_t info_bytes = align_up((size_t)n_pairs * sizeof(PairInfo), 256);
+    BatchArgs a;
+    a.query = query_dev;
+    a.train = train_dev;
+    a.query_rows = query_rows;
+    a.train_rows = train_rows;
+    a.out_rows = out_rows;
+    a.pairs = reinterpret_cast<const PairEntry *>(pairs_dev);
+    a.n_pairs = n_pairs;
+    a.item_capacity = out_rows / 256 + n_pairs + 1;
+    a.info = reinterpret_cast<PairInfo *>(ws);
+    a.state = reinterpret_cast<BatchState *>(ws + info_bytes);
+    a.item_pair = reinterpret_cast<int32_t *>(ws + info_bytes + 256);
+    a.k = k;
+    a.ratio = ratio;
+    a.idx = idx_dev;
+    a.dist = dist_dev;
+    a.accept = accept_dev;
+    a.flags = h->flags_dev;
+    a.num_cus = h->num_cus;
+    a.mfma = path != LATCH_PATH_POPCOUNT;
+    return a;
+}
+
+ExtractArgs batch_extract_args(latch_handle h, const latch_image *images_dev, int n_images,
+                               const int32_t *image_id_dev, const latch_keypoint *kps_dev,
+                               int64_t max_kps, const int64_t *n_kps_dev, uint32_t *desc_dev)
+{
+    ExtractArgs a;
+    a.img = nullptr;
+    a.height = a.width = a.pitch = 0;
+    a.table = reinterpret_cast<const ImageEntry *>(images_dev);
+    a.image_id = image_id_dev;
+    a.n_images = n_images;
+    a.kps = reinterpret_cast<const float4 *>(kps_dev);
+    a.n = max_kps;
+    a.n_dev = n_kps_dev;
+    a.rot = h->rot_dev;
+    a.trip_off = h->trip_off_dev;
+    a.desc = desc_dev;
+    a.flags = h->flags_dev;
+    a.num_cus = h->num_cus;
+    return a;
+}
+
 }  // namespace
+
+struct latch_plan_ctx {
+    latch_handle h = nullptr;
+    uint8_t *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
 
 extern "C" {
 
@@ -283,20 +349,8 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
     if (max_kps == 0) return LATCH_OK;
     if (!images_dev || !image_id_dev || !kps_dev || !desc_dev || n_images == 0)
         return fail(h, LATCH_EINVAL, "null buffer or empty image table");
-    ExtractArgs a;
-    a.img = nullptr;
-    a.height = a.width = a.pitch = 0;
-    a.table = reinterpret_cast<const ImageEntry *>(images_dev);
-    a.image_id = image_id_dev;
-    a.n_images = n_images;
-    a.kps = reinterpret_cast<const float4 *>(kps_dev);
-    a.n = max_kps;
-    a.n_dev = n_kps_dev;
-    a.rot = h->rot_dev;
-    a.trip_off = h->trip_off_dev;
-    a.desc = desc_dev;
-    a.flags = h->flags_dev;
-    a.num_cus = h->num_cus;
+    const ExtractArgs a = batch_extract_args(h, images_dev, n_images, image_id_dev, kps_dev,
+                                             max_kps, n_kps_dev, desc_dev);
     hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
 }
@@ -397,35 +451,81 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
         return fail(h, LATCH_EINVAL, "null buffer");
     if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
 
-    const int64_t item_capacity = out_rows / 256 + n_pairs + 1;
-    const size_t info_bytes = align_up((size_t)n_pairs * sizeof(PairInfo), 256);
-    const size_t state_bytes = 256;
-    const size_t map_bytes = align_up((size_t)item_capacity * sizeof(int32_t), 256);
-    int rc = ensure_workspace(h, info_bytes + state_bytes + map_bytes);
+    int rc = ensure_workspace(h, batch_workspace_bytes(n_pairs, out_rows));
     if (rc != LATCH_OK) return rc;
-    BatchArgs a;
-    a.query = query_dev;
-    a.train = train_dev;
-    a.query_rows = query_rows;
-    a.train_rows = train_rows;
-    a.out_rows = out_rows;
-    a.pairs = reinterpret_cast<const PairEntry *>(pairs_dev);
-    a.n_pairs = n_pairs;
-    a.item_capacity = item_capacity;
-    a.info = reinterpret_cast<PairInfo *>(h->ws);
-    a.state = reinterpret_cast<BatchState *>(h->ws + info_bytes);
-    a.item_pair = reinterpret_cast<int32_t *>(h->ws + info_bytes + state_bytes);
-    a.k = k;
-    a.ratio = ratio;
-    a.idx = idx_dev;
-    a.dist = dist_dev;
-    a.accept = accept_dev;
-    a.flags = h->flags_dev;
-    a.num_cus = h->num_cus;
-    a.mfma = path == LATCH_PATH_MFMA;
+    const BatchArgs a = batch_args(h, h->ws, query_dev, query_rows, train_dev, train_rows,
+                                   pairs_dev, n_pairs, k, ratio, idx_dev, dist_dev, accept_dev,
+                                   out_rows, path);
     hipError_t e = timed_launch(h, a.mfma ? "knn_batch_mfma" : "knn_batch_popcount", stream,
                                 [&] { return launch_knn_batch(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched knn launch");
+}
+
+int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
+{
+    if (!h || !d || !out) return LATCH_EINVAL;
+    *out = nullptr;
+    h->last_error.clear();
+    if (d->max_kps < 0 || d->max_kps > LATCH_MAX_ROWS || d->n_images < 1 || d->n_pairs < 0 ||
+        d->out_rows < 0 || d->out_rows > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "bad plan sizes");
+    if (d->k != 1 && d->k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", d->k);
+    if (!(d->ratio > 0.0f && d->ratio <= 1.0f))
+        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)d->ratio);
+    if (d->path != LATCH_PATH_AUTO && d->path != LATCH_PATH_MFMA && d->path != LATCH_PATH_POPCOUNT)
+        return fail(h, LATCH_EINVAL, "unknown path %d", d->path);
+    if (!d->images || !d->image_id || !d->kps || !d->desc ||
+        (d->n_pairs > 0 && (!d->pairs || !d->idx || !d->dist)))
+        return fail(h, LATCH_EINVAL, "null buffer");
+
+    latch_plan_ctx *p = new latch_plan_ctx();
+    p->h = h;
+    hipError_t e = hipMalloc((void **)&p->ws, batch_workspace_bytes(d->n_pairs, d->out_rows));
+    if (e != hipSuccess) {
+        delete p;
+        return hip_fail(h, e, "hipMalloc(plan workspace)");
+    }
+    const ExtractArgs ea = batch_extract_args(h, d->images, d->n_images, d->image_id, d->kps,
+                                              d->max_kps, d->n_kps, d->desc);
+    const BatchArgs ba = batch_args(h, p->ws, d->desc, d->max_kps, d->desc, d->max_kps, d->pairs,
+                                    d->n_pairs, d->k, d->ratio, d->idx, d->dist, d->accept,
+                                    d->out_rows, d->path);
+    hipStream_t s = nullptr;
+    e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess && d->max_kps > 0) e = launch_extract(ea, s);
+    if (e == hipSuccess && d->n_pairs > 0) e = launch_knn_batch(ba, s);
+    hipGraph_t graph = nullptr;
+    if (s) {
+        const hipError_t e2 = hipStreamEndCapture(s, &graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&p->exec, graph, nullptr, nullptr, 0);
+    p->graph = graph;
+    if (s) (void)hipStreamDestroy(s);
+    if (e != hipSuccess) {
+        latch_plan_destroy(p);
+        return hip_fail(h, e, "plan capture");
+    }
+    *out = p;
+    return LATCH_OK;
+}
+
+int latch_plan_run(latch_plan p, hipStream_t stream)
+{
+    if (!p) return LATCH_EINVAL;
+    const hipError_t e = hipGraphLaunch(p->exec, stream);
+    return e == hipSuccess ? LATCH_OK : hip_fail(p->h, e, "graph launch");
+}
+
+void latch_plan_destroy(latch_plan p)
+{
+    if (!p) return;
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->ws) (void)hipFree(p->ws);
+    delete p;
 }
 
 int latch_check_errors(latch_handle h, hipStream_t stream, uint32_t *flags_out, int clear)
