@@ -259,6 +259,25 @@ const char *latch_last_error(latch_handle h);
 int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
 
 /*
+ * Tuning.  LATCH_PATH_AUTO picks the matcher path from a per-handle table
+ * indexed by size buckets, bucket(n) = min(7, floor(log2(max(n, 1)) / 2)),
+ * and the split planner of hamming_knn aims at the given number of
+ * workgroups per CU.  Defaults: MFMA everywhere, 2 (MFMA) and 8 (popcount)
+ * workgroups per CU.  Tuning never changes results, only speed.
+ */
+typedef struct {
+    int8_t path[8][8];               /* [bucket(nq)][bucket(nt)]: LATCH_PATH_MFMA or _POPCOUNT */
+    int8_t batch_path;               /* path of batched matching under LATCH_PATH_AUTO */
+    int8_t reserved[3];
+    int32_t mfma_groups_per_cu;      /* >= 1 */
+    int32_t popcount_groups_per_cu;  /* >= 1 */
+} latch_tuning;
+
+int latch_get_tuning(latch_handle h, latch_tuning *out);
+/* LATCH_ERANGE if a path entry is not MFMA or POPCOUNT or a target is < 1. */
+int latch_set_tuning(latch_handle h, const latch_tuning *t);
+
+/*
  * Per-kernel timing with HIP events, for measurement.  While enabled, every
  * kernel the handle launches is bracketed by two hipEventRecord calls on the
  * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops

@@ -1,0 +1,157 @@
+"""Autotuner for the matcher: picks, per (query count, train count) size
+bucket, the faster of the int8-MFMA and popcount paths, the path for
+batched matching, and the split planner's workgroups-per-CU target.  It
+measures the library's own kernels (HIP events recorded by the library on
+its launch stream) on random descriptors and caches the result per device
+and library version.
+
+Tuning never changes results (every path is exact), only speed.
+
+    python -m paper_1609_03986_amd.autotune [--cache PATH] [--quick]
+"""
+import json
+import os
+import sys
+
+import numpy as np
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "latch_gfx950", "autotune.json")
+MFMA, POPCOUNT = 1, 2
+
+
+def bucket_shape(b):
+    """A representative size of bucket b (bucket(n) = floor(log2 n / 2))."""
+    return 2 ** (2 * b + 1)
+
+
+def choose(timings):
+    """timings: {candidate: seconds}.  The fastest candidate; ties go to the
+    first candidate in insertion order."""
+    best = None
+    for c, t in timings.items():
+        if best is None or t < timings[best]:
+            best = c
+    return best
+
+
+def fill_table(measured):
+    """measured: {(qb, tb): path}.  An 8 x 8 table whose unmeasured cells take
+    the choice of the nearest measured cell (ties to the larger bucket)."""
+    table = [[MFMA] * 8 for _ in range(8)]
+    if not measured:
+        return table
+    keys = list(measured)
+    for i in range(8):
+        for j in range(8):
+            k = min(keys, key=lambda ab: (abs(ab[0] - i) + abs(ab[1] - j), -ab[0], -ab[1]))
+            table[i][j] = measured[k]
+    return table
+
+
+def _time_knn(lat, q, t, path, reps):
+    import torch
+    lat.knn(q, t, path=path)                         # warm-up, workspace growth
+    torch.cuda.synchronize()
+    lat.timing(True)
+    for _ in range(reps):
+        lat.knn(q, t, path=path)
+    torch.cuda.synchronize()
+    total = 0.0
+    for name in ("knn_mfma", "knn_popcount", "knn_merge"):
+        n, ms = lat.timing_read(name)
+        total += ms
+    lat.timing(False)
+    return total / reps * 1e-3
+
+
+def tune(lat, buckets=None, reps=5, seed=0, log=None):
+    """Measure and install a tuning on the handle `lat` (binding.Latch);
+    returns it as a dict."""
+    import torch
+    from . import synth
+    from .binding import Tuning
+    g = np.random.default_rng(seed)
+    if buckets is None:
+        buckets = [(qb, tb) for qb in (2, 4, 6, 7) for tb in (4, 6, 7)]
+    cap = 1 << 17
+    rows = max(min(bucket_shape(b), cap) for ab in buckets for b in ab)
+    pool = torch.from_numpy(synth.random_descriptors(g, rows).view(np.int32)).cuda()
+    base = lat.get_tuning().to_dict()
+    measured = {}
+    for qb, tb in buckets:
+        nq, nt = min(bucket_shape(qb), cap), min(bucket_shape(tb), cap)
+        q, t = pool[:nq], pool[rows - nt:]
+        ts = {MFMA: _time_knn(lat, q, t, "mfma", reps),
+              POPCOUNT: _time_knn(lat, q, t, "popcount", reps)}
+        measured[(qb, tb)] = choose(ts)
+        if log:
+            log("bucket (%d, %d) nq=%d nt=%d: mfma %.1f us, popcount %.1f us" %
+                (qb, tb, nq, nt, ts[MFMA] * 1e6, ts[POPCOUNT] * 1e6))
+    tuning = dict(base)
+    tuning["path"] = fill_table(measured)
+    # Split planner target on the 10,000 x 10,000 shape.
+    q, t = pool[:10000], pool[rows - 10000:] if rows >= 20000 else pool[:10000]
+    targets = {}
+    for w in (1, 2, 3, 4):
+        trial = dict(tuning, mfma_groups_per_cu=w)
+        lat.set_tuning(Tuning.from_dict(trial))
+        targets[w] = _time_knn(lat, q, t, "mfma", reps)
+    tuning["mfma_groups_per_cu"] = choose(targets)
+    if log:
+        log("mfma workgroups per CU: %s -> %d" %
+            ({w: round(v * 1e6, 1) for w, v in targets.items()}, tuning["mfma_groups_per_cu"]))
+    tuning["batch_path"] = tuning["path"][6][6]
+    lat.set_tuning(Tuning.from_dict(tuning))
+    return tuning
+
+
+def cache_key():
+    import torch
+    from .binding import latch_version
+    return "%s|%s" % (torch.cuda.get_device_name(0), latch_version())
+
+
+def load(lat, path=DEFAULT_CACHE):
+    """Install a cached tuning for this device and library version, if any."""
+    from .binding import Tuning
+    try:
+        entries = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    t = entries.get(cache_key())
+    if t is not None:
+        lat.set_tuning(Tuning.from_dict(t))
+    return t
+
+
+def save(tuning, path=DEFAULT_CACHE):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    try:
+        entries = json.load(open(path))
+    except (OSError, ValueError):
+        entries = {}
+    entries[cache_key()] = tuning
+    tmp = path + ".tmp%d" % os.getpid()
+    with open(tmp, "w") as f:
+        json.dump(entries, f, indent=1)
+    os.replace(tmp, path)
+
+
+def main(argv=None):
+    import argparse
+    from . import synth
+    from .binding import Latch
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--cache", default=DEFAULT_CACHE)
+    ap.add_argument("--quick", action="store_true", help="three buckets only")
+    args = ap.parse_args(argv)
+    lat = Latch(synth.triplet_table())
+    buckets = [(2, 6), (6, 6), (7, 7)] if args.quick else None
+    t = tune(lat, buckets, log=lambda m: print(m, flush=True))
+    save(t, args.cache)
+    print(json.dumps({"cache": args.cache, "tuning": t}), flush=True)
+    lat.close()
+
+
+if __name__ == "__main__":
+    sys.exit(main())

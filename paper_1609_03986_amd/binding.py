@@ -33,6 +33,7 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
 # Every symbol include/latch.h declares.
 EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "hamming_knn",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
+           "latch_get_tuning", "latch_set_tuning",
            "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
@@ -55,6 +56,11 @@ def load_library():
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError("liblatch.so is not built; run `python -m paper_1609_03986_amd.build`")
+    # torch ships its own libamdhip64 with the same soname as the system one.
+    # Loading torch first makes the dynamic linker bind liblatch.so to that
+    # runtime; loading liblatch.so first would put two HIP runtimes in the
+    # process, and the second one to initialise finds no GPU.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P, I, I64, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
     lib.latch_create.argtypes = [ctypes.POINTER(P), P]
@@ -74,6 +80,10 @@ def load_library():
     lib.latch_plan_run.restype = I
     lib.latch_plan_destroy.argtypes = [P]
     lib.latch_plan_destroy.restype = None
+    lib.latch_get_tuning.argtypes = [P, P]
+    lib.latch_get_tuning.restype = I
+    lib.latch_set_tuning.argtypes = [P, P]
+    lib.latch_set_tuning.restype = I
     lib.hamming_knn.restype = I
     lib.latch_check_errors.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint32), I]
     lib.latch_check_errors.restype = I
@@ -260,6 +270,48 @@ def hamming_knn_batch(h, query, train, pairs, out_rows, k=2, ratio=0.8, path="au
     return idx, dist, accept
 
 
+class Tuning(ctypes.Structure):
+    """latch_tuning: path per (bucket(nq), bucket(nt)), batch path, split targets."""
+    _fields_ = [("path", (ctypes.c_int8 * 8) * 8), ("batch_path", ctypes.c_int8),
+                ("reserved", ctypes.c_int8 * 3), ("mfma_groups_per_cu", ctypes.c_int32),
+                ("popcount_groups_per_cu", ctypes.c_int32)]
+
+    def to_dict(self):
+        return {"path": [[int(self.path[i][j]) for j in range(8)] for i in range(8)],
+                "batch_path": int(self.batch_path),
+                "mfma_groups_per_cu": int(self.mfma_groups_per_cu),
+                "popcount_groups_per_cu": int(self.popcount_groups_per_cu)}
+
+    @classmethod
+    def from_dict(cls, d):
+        t = cls()
+        for i in range(8):
+            for j in range(8):
+                t.path[i][j] = d["path"][i][j]
+        t.batch_path = d["batch_path"]
+        t.mfma_groups_per_cu = d["mfma_groups_per_cu"]
+        t.popcount_groups_per_cu = d["popcount_groups_per_cu"]
+        return t
+
+
+def size_bucket(n):
+    """Bucket of a size for the tuning table: min(7, floor(log2(max(n, 1)) / 2))."""
+    b = 0
+    while b < 7 and (int(n) >> (2 * (b + 1))) > 0:
+        b += 1
+    return b
+
+
+def latch_get_tuning(h):
+    t = Tuning()
+    _check(h, load_library().latch_get_tuning(h, ctypes.byref(t)))
+    return t
+
+
+def latch_set_tuning(h, t):
+    _check(h, load_library().latch_set_tuning(h, ctypes.byref(t)))
+
+
 class _PlanDesc(ctypes.Structure):
     _fields_ = [("images", ctypes.c_void_p), ("n_images", ctypes.c_int32),
                 ("image_id", ctypes.c_void_p), ("kps", ctypes.c_void_p),
@@ -349,6 +401,12 @@ class Latch:
 
     def knn_batch(self, query, train, pairs, out_rows, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn_batch(self.h, query, train, pairs, out_rows, k, ratio, path, **kw)
+
+    def get_tuning(self):
+        return latch_get_tuning(self.h)
+
+    def set_tuning(self, t):
+        latch_set_tuning(self.h, t)
 
     def plan(self, *args, **kw):
         return Plan(self.h, *args, **kw)

@@ -20,6 +20,7 @@ struct latch_ctx {
     uint32_t *flags_dev = nullptr;     // sticky error word
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
+    latch_tuning tuning;               // LATCH_PATH_AUTO table and split targets
     std::string last_error;
     // Event timing (latch_timing_enable).
     bool timing = false;
@@ -139,9 +140,25 @@ void release_timed(latch_handle h)
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Train splits: enough (query group, split) workgroups to fill every CU
-// once (two MFMA workgroups or eight popcount workgroups resident per CU),
+// once (by default two MFMA or eight popcount workgroups per CU),
 // at least 8 tiles (256 rows) per split, split-local indices below 2^21 - 1.
-KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus)
+int size_bucket(int64_t n)
+{
+    int b = 0;
+    while (b < 7 && (n >> (2 * (b + 1))) > 0) ++b;
+    return b;
+}
+
+void default_tuning(latch_tuning *t)
+{
+    std::memset(t, 0, sizeof *t);
+    std::memset(t->path, LATCH_PATH_MFMA, sizeof t->path);
+    t->batch_path = LATCH_PATH_MFMA;
+    t->mfma_groups_per_cu = 2;
+    t->popcount_groups_per_cu = 8;
+}
+
+KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuning &tune)
 {
     KnnPlan p;
     p.nq = nq;
@@ -153,7 +170,8 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus)
         return p;
     }
     const int64_t qgroups = (nq + 255) / 256;
-    const int64_t slots = (int64_t)num_cus * (path == LATCH_PATH_MFMA ? 2 : 8);
+    const int64_t slots = (int64_t)num_cus *
+                          (path == LATCH_PATH_MFMA ? tune.mfma_groups_per_cu : tune.popcount_groups_per_cu);
     int64_t nsplit = qgroups >= slots ? 1 : slots / qgroups;
     const int64_t max_by_size = (tiles + 7) / 8;
     if (nsplit > max_by_size) nsplit = max_by_size;
@@ -254,6 +272,7 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
         if (triplets_host[i] < kPatchR || triplets_host[i] > kWin - 1 - kPatchR) return LATCH_ERANGE;
 
     latch_ctx *h = new latch_ctx();
+    default_tuning(&h->tuning);
     hipError_t e = hipGetDevice(&h->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device);
@@ -372,9 +391,9 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
     if (nq == 0) return LATCH_OK;
     if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
         return fail(h, LATCH_EINVAL, "null buffer");
-    if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
+    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
 
-    const KnnPlan plan = plan_knn(nq, nt, path, h->num_cus);
+    const KnnPlan plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
     const size_t partial_bytes = align_up((size_t)plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
     int rc = ensure_workspace(h, partial_bytes);
     if (rc != LATCH_OK) return rc;
@@ -396,6 +415,27 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
         return launch_knn_merge(partial, plan, k, ratio, idx_dev, dist_dev, accept_dev, stream);
     });
     if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    return LATCH_OK;
+}
+
+int latch_get_tuning(latch_handle h, latch_tuning *out)
+{
+    if (!h || !out) return LATCH_EINVAL;
+    *out = h->tuning;
+    return LATCH_OK;
+}
+
+int latch_set_tuning(latch_handle h, const latch_tuning *t)
+{
+    if (!h || !t) return LATCH_EINVAL;
+    auto ok_path = [](int p) { return p == LATCH_PATH_MFMA || p == LATCH_PATH_POPCOUNT; };
+    for (int i = 0; i < 8; ++i)
+        for (int j = 0; j < 8; ++j)
+            if (!ok_path(t->path[i][j])) return fail(h, LATCH_ERANGE, "tuning path[%d][%d]", i, j);
+    if (!ok_path(t->batch_path)) return fail(h, LATCH_ERANGE, "tuning batch_path");
+    if (t->mfma_groups_per_cu < 1 || t->popcount_groups_per_cu < 1)
+        return fail(h, LATCH_ERANGE, "tuning workgroup targets must be >= 1");
+    h->tuning = *t;
     return LATCH_OK;
 }
 
@@ -449,7 +489,7 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
     if (!pairs_dev || !idx_dev || !dist_dev || (query_rows > 0 && !query_dev) ||
         (train_rows > 0 && !train_dev))
         return fail(h, LATCH_EINVAL, "null buffer");
-    if (path == LATCH_PATH_AUTO) path = LATCH_PATH_MFMA;
+    if (path == LATCH_PATH_AUTO) path = h->tuning.batch_path;
 
     int rc = ensure_workspace(h, batch_workspace_bytes(n_pairs, out_rows));
     if (rc != LATCH_OK) return rc;
@@ -489,7 +529,8 @@ int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
                                               d->max_kps, d->n_kps, d->desc);
     const BatchArgs ba = batch_args(h, p->ws, d->desc, d->max_kps, d->desc, d->max_kps, d->pairs,
                                     d->n_pairs, d->k, d->ratio, d->idx, d->dist, d->accept,
-                                    d->out_rows, d->path);
+                                    d->out_rows,
+                                    d->path == LATCH_PATH_AUTO ? h->tuning.batch_path : d->path);
     hipStream_t s = nullptr;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
