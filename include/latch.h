@@ -158,8 +158,11 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
  *   accept_dev: uint8[nq] or NULL: 1 iff nt >= 2 and d1 < ratio * d2, evaluated
  *              exactly (the second neighbour is always searched, also for k = 1).
  *   path:      a latch_path value; every path returns identical results.
- * nq == 0 is a no-op.  nq and nt must be < 2^31.  May grow the handle's
- * workspace (a device allocation, LATCH_ENOMEM on failure).
+ * nq == 0 is a no-op.  nq and nt must be < 2^31.  The train rows are split
+ * over workgroups; with more than one split a merge kernel follows.  May
+ * grow the handle's workspace (a device allocation, LATCH_ENOMEM on
+ * failure); calls on one handle must not overlap in time on different
+ * streams.
  */
 int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
                 const uint32_t *train_dev, int64_t nt, int k, float ratio,

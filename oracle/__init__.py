@@ -67,6 +67,8 @@ def _load():
         lib.oracle_knn.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = i32
+        lib.oracle_set_threads.argtypes = [i32]
+        lib.oracle_set_threads.restype = None
         _lib = lib
     return _lib
 
@@ -74,6 +76,11 @@ def _load():
 def num_threads():
     """OpenMP threads used by extract() and knn()."""
     return int(_load().oracle_num_threads())
+
+
+def set_threads(n):
+    """Set the OpenMP thread count of extract() and knn() (n >= 1)."""
+    _load().oracle_set_threads(int(n))
 
 
 def _ptr(a):

@@ -272,3 +272,9 @@ int oracle_num_threads(void)
 {
     return omp_get_max_threads();
 }
+
+/* Sets that number (n >= 1); used to time the oracle on one core. */
+void oracle_set_threads(int n)
+{
+    omp_set_num_threads(n < 1 ? 1 : n);
+}

@@ -37,7 +37,7 @@ EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batc
            "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
-KERNELS = ("extract", "knn_prep", "knn_mfma", "knn_popcount", "knn_merge")
+KERNELS = ("extract", "knn_mfma", "knn_popcount", "knn_merge", "knn_batch_mfma", "knn_batch_popcount")
 
 
 class LatchError(RuntimeError):

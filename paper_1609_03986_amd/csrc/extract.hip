@@ -3,12 +3,17 @@
 // A workgroup of two wavefronts computes one descriptor at a time
 // (grid-stride over keypoints):
 //   1. resampling rule steps 1-3 on the keypoint (uniform across the group);
-//   2. gather of the 48 x 48 upright window (steps 4-5): thread t owns window
-//      dwords d = t + 128 m, i.e. 20 or 16 samples, issued as independent
-//      byte loads one keypoint ahead so that their latency overlaps the
-//      previous descriptor's arithmetic;
-//   3. eight byte-shifted copies of the window in LDS, so that every 7-byte
-//      patch row is the head of one 8-byte-aligned ds_read_b64;
+//   2. gather of the 48 x 48 upright window (steps 4-5).  The sample offsets
+//      of window positions (u, v), (-v, u), (-u, -v), (v, -u) are (ox, oy),
+//      (-oy, ox), (-ox, -oy), (oy, -ox): quarter turns of the same rounded
+//      pair, because the rounding is odd-symmetric.  So the 47 x 47 core is
+//      552 such orbits plus the centre, each costing one pair of roundings
+//      for four samples, and row 0 and column 0 (95 samples) are done one by
+//      one.  The byte loads are issued one keypoint ahead so that their
+//      latency overlaps the previous descriptor's arithmetic;
+//   3. the samples are written to a plain window in LDS, and a copy pass
+//      builds eight byte-shifted copies of it in which every 7-byte patch
+//      row is one 8-byte-aligned quadword with a zero last byte;
 //   4. Eq. 1 (Sec. 3.1) for 512 triplets: each wavefront takes 4 rounds of 64
 //      lanes, one triplet per lane per round, in exact integer arithmetic;
 //   5. a 64-bit ballot per round packs the bits; 8 lanes per wavefront store
@@ -17,27 +22,45 @@
 // Patch distances.  With A, C the 7 x 7 patches of the anchor and one
 // companion, ||A - C||^2 = sum A^2 + sum C^2 - 2 sum A C.  sum A^2 is shared by
 // both sides of Eq. 1, so bit = [sum C1^2 - 2 sum A C1 > sum C2^2 - 2 sum A C2].
-// Each 7-pixel row is 8 packed u8 (the 8th byte masked to zero in the
-// companion operands) and each sum is a chain of v_dot4_u32_u8.  All sums are
-// < 49 * 255^2 < 2^22, so the int32 result equals the exact integer one.
+// Each patch row is a quadword of 7 u8 and a zero byte, and each sum is a
+// chain of v_dot4_u32_u8.  All sums are < 49 * 255^2 < 2^22, so the int32
+// result equals the exact integer one.
 //
 // The paper's CUDA kernel (Sec. 3.2) spreads one descriptor over 32 warps of
 // a 1024-thread block with float32 patches in shared memory; here two 64-lane
-// wavefronts share an 18 KB byte window (eight LDS windows per CU, four
-// wavefronts per SIMD) and synchronise three times per descriptor.
+// wavefronts share a 19.3 KB byte window (eight per CU, four wavefronts per
+// SIMD) and synchronise twice per descriptor.
 #include "internal.h"
 
 namespace latch {
 namespace {
 
 constexpr int kThreads = kExtractWaves * 64;             // 128: two wavefronts per window
-constexpr int kGatherDwords = kWin * kWin / 4;            // 576
-constexpr int kRowDwords = kRowBytes / 4;                 // 12
-constexpr int kGatherPerThread = (kGatherDwords + kThreads - 1) / kThreads;   // 5
-constexpr int kSamples = 4 * kGatherPerThread;            // 20
 constexpr int kRoundsPerWave = 8 / kExtractWaves;         // 4
-static_assert(kGatherDwords == kThreads * (kGatherPerThread - 1) + 64,
-              "the last gather dword row belongs to wavefront 0 exactly");
+
+// Gather work per window: orbits with representative (u, v), u in [1, 23],
+// v in [0, 23], and single samples (row 0, column 0, the centre).
+constexpr int kOrbitU = kHalf - 1;                        // 23
+constexpr int kOrbits = kOrbitU * kHalf;                  // 552
+constexpr int kSingles = 2 * kWin;                        // 96 = 48 + 47 + 1
+constexpr int kFullSlots = 4;                             // orbit slots every thread has
+constexpr int kSlot4Orbits = kOrbits - kFullSlots * kThreads;     // 40 (threads 0..39)
+constexpr int kSlot4Singles = kThreads - kSlot4Orbits;            // 88 (threads 40..127)
+constexpr int kSlot5Singles = kSingles - kSlot4Singles;           // 8 (threads 0..7)
+constexpr int kSlots = kFullSlots + 2;
+constexpr int kSamples = 4 * (kFullSlots + 1) + 1;                // 21 bytes in flight per thread
+static_assert(kSlot4Orbits > 0 && kSlot4Orbits <= 64 && kSlot5Singles > 0 && kSlot5Singles <= 64,
+              "slot 4 orbits and slot 5 singles belong to wavefront 0");
+static_assert(4 * kOrbits + 1 + (kSingles - 1) == kWin * kWin, "every window byte once");
+
+// Raw window byte of position (u, v): kRawBase + (v + 24) kRawStride + u + 24.
+constexpr int kRawCentre = kRawBase + kHalf * kRawStride + kHalf;
+// Copy pass: units (row y, quadword q), 240 per window, unit e = 5 y + q.
+constexpr int kCopyUnits = kWin * kCopyQwords;
+static_assert(kCopyUnits > kThreads && kCopyUnits <= 2 * kThreads, "two copy units per thread");
+static_assert(kWinLdsBytes * 8 <= kLdsPerCu, "eight windows per CU");
+
+typedef const __attribute__((address_space(1))) uint8_t GlobalByte;
 
 // n / 2^22 rounded half away from zero, for |n| < 2^31 - 2^21.
 // n >= 0: floor((n + 2^21) / 2^22).  n < 0: floor((n + 2^21 - 1) / 2^22),
@@ -82,7 +105,6 @@ struct Keypoint {
     bool interior;  // every sample lies inside the image: no clamping needed
     int cx, cy;
     int c, s, sq;   // C[b], S[b] (Q14) and the Q8 scale
-    int ca, sb;     // sq * C[b], sq * S[b]
     const uint8_t *img;
     int height, width, pitch;
 };
@@ -179,8 +201,6 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bo
     k.ok = (f >> 16) & 1;
     k.interior = (f >> 17) & 1;
     *bad_image = (f >> 18) & 1;
-    k.ca = k.sq * k.c;     // |ca|, |sb| <= 2^24
-    k.sb = k.sq * k.s;
     const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane(kb.img_lo, j);
     const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane(kb.img_hi, j);
     k.img = reinterpret_cast<const uint8_t *>(lo | (hi << 32));
@@ -190,55 +210,187 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bo
     return k;
 }
 
-// Window coordinates (u, v) = (4 (d % 12) - 24, d / 12 - 24) of this
-// thread's window dwords d = tid + 128 m, packed as (u & 0xffff) | (v << 16).
-__device__ __forceinline__ void thread_coords(int tid, int (&uv)[kGatherPerThread])
+// This thread's gather slots.  Slot m < 4 is orbit tid + 128 m; slot 4 is
+// orbit 512 + tid (tid < 40) or single tid - 40; slot 5 is single 88 + tid
+// (tid < 8).  uv packs (u & 0xffff) | v << 16 of the representative
+// position; raw packs the raw-window byte addresses of its first two orbit
+// members (the other two are 2 kRawCentre minus these).
+struct Slots {
+    int uv[kSlots];
+    uint32_t raw[kSlots];
+};
+
+__device__ __forceinline__ int pack_uv(int u, int v)
 {
+    return (u & 0xffff) | (v << 16);
+}
+
+__device__ __forceinline__ uint32_t raw_addr(int u, int v)
+{
+    return (uint32_t)(kRawCentre + v * kRawStride + u);
+}
+
+__device__ __forceinline__ void orbit_slot(int o, int &uv, uint32_t &raw)
+{
+    const int v = o / kOrbitU, u = o - kOrbitU * v + 1;
+    uv = pack_uv(u, v);
+    raw = raw_addr(u, v) | (raw_addr(-v, u) << 16);
+}
+
+// Single s: row 0 (v = -24) for s < 48, column 0 (u = -24, v = -23..23) for
+// s < 95, the centre for s = 95.
+__device__ __forceinline__ void single_slot(int s, int &uv, uint32_t &raw)
+{
+    int u, v;
+    if (s < kWin) {
+        u = s - kHalf;
+        v = -kHalf;
+    } else if (s < kSingles - 1) {
+        u = -kHalf;
+        v = s - kWin - (kHalf - 1);
+    } else {
+        u = v = 0;
+    }
+    uv = pack_uv(u, v);
+    raw = raw_addr(u, v);
+}
+
+__device__ __forceinline__ Slots thread_slots(int tid)
+{
+    Slots sl;
 #pragma unroll
-    for (int m = 0; m < kGatherPerThread; ++m) {
-        const int d = min(tid + kThreads * m, kGatherDwords - 1);
-        const int i = d / kRowDwords;
-        uv[m] = ((4 * (d - kRowDwords * i) - kHalf) & 0xffff) | ((i - kHalf) << 16);
+    for (int m = 0; m < kFullSlots; ++m) orbit_slot(tid + kThreads * m, sl.uv[m], sl.raw[m]);
+    if (tid < kSlot4Orbits)
+        orbit_slot(kFullSlots * kThreads + tid, sl.uv[4], sl.raw[4]);
+    else
+        single_slot(tid - kSlot4Orbits, sl.uv[4], sl.raw[4]);
+    single_slot(kSlot4Singles + min(tid, kSlot5Singles - 1), sl.uv[5], sl.raw[5]);
+    return sl;
+}
+
+// Rule step 4 for one position: the rounded offsets of (u, v).
+// sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
+// sq <= 2^10, so every product is exact and full rate.
+__device__ __forceinline__ void offsets(const Keypoint &k, int uv, int &ox, int &oy)
+{
+    const int u = (int)(short)(uv & 0xffff);
+    const int v = uv >> 16;
+    ox = round_q22(mul_i24(mad_i24(k.c, u, mul_i24(-k.s, v)), k.sq));
+    oy = round_q22(mul_i24(mad_i24(k.s, u, mul_i24(k.c, v)), k.sq));
+}
+
+// Rule step 5 for the four members of an orbit: offsets (ox, oy), (-oy, ox),
+// (-ox, -oy), (oy, -ox) from the centre.  Members 1..3 are loaded only when
+// `whole` (slot 4 holds a single sample in some lanes: member 0 only).  The
+// members of a position with |u|, |v| <= 24 are positions of the same kind,
+// so the interior test covers all four.
+__device__ __forceinline__ void gather_orbit(const Keypoint &k, GlobalByte *img, int uv, bool whole,
+                                             uint32_t &g0, uint32_t &g1, uint32_t &g2, uint32_t &g3)
+{
+    int ox, oy;
+    offsets(k, uv, ox, oy);
+    uint32_t a0, a1, a2, a3;
+    if (k.interior) {
+        // Every sample is inside the image, so |offset| * pitch < 2^31 and the
+        // 24-bit multiply-adds are exact.
+        const int base = k.cy * k.pitch + k.cx;
+        const int t = mad_i24(oy, k.pitch, ox);
+        const int w = mad_i24(ox, k.pitch, -oy);
+        a0 = (uint32_t)(base + t);
+        a1 = (uint32_t)(base + w);
+        a2 = (uint32_t)(base - t);
+        a3 = (uint32_t)(base - w);
+    } else {
+        const int xm = k.width - 1, ym = k.height - 1;
+        a0 = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
+        a1 = (uint32_t)mad_i24(clamp_med3(k.cy + ox, 0, ym), k.pitch, clamp_med3(k.cx - oy, 0, xm));
+        a2 = (uint32_t)mad_i24(clamp_med3(k.cy - oy, 0, ym), k.pitch, clamp_med3(k.cx - ox, 0, xm));
+        a3 = (uint32_t)mad_i24(clamp_med3(k.cy - ox, 0, ym), k.pitch, clamp_med3(k.cx + oy, 0, xm));
+    }
+    g0 = img[a0];
+    if (whole) {
+        g1 = img[a1];
+        g2 = img[a2];
+        g3 = img[a3];
     }
 }
 
-// Rule steps 4-5: issue the byte loads of this thread (window dwords
-// d = tid + 128 m, bytes b = 0..3, i.e. row d / 12, column 4 (d % 12) + b);
-// dword m exists for m < 4, and for m = 4 in the first wavefront only.
-// sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
-// sq <= 2^10, so every product is exact and full rate.
-__device__ __forceinline__ void issue_gather(const Keypoint &k, bool has_last,
-                                             const int (&uv)[kGatherPerThread],
+__device__ __forceinline__ uint32_t gather_single(const Keypoint &k, GlobalByte *img, int uv)
+{
+    int ox, oy;
+    offsets(k, uv, ox, oy);
+    if (k.interior) return img[(uint32_t)(k.cy * k.pitch + k.cx + mad_i24(oy, k.pitch, ox))];
+    const int x = clamp_med3(k.cx + ox, 0, k.width - 1);
+    const int y = clamp_med3(k.cy + oy, 0, k.height - 1);
+    return img[(uint32_t)mad_i24(y, k.pitch, x)];
+}
+
+// Issue this thread's byte loads for keypoint k (results land in g).
+__device__ __forceinline__ void issue_gather(const Keypoint &k, int tid, bool wave0, const Slots &sl,
                                              uint32_t (&g)[kSamples])
 {
-    const uint8_t *__restrict__ img = k.img;
-    const int height = k.height, width = k.width, pitch = k.pitch;
+    GlobalByte *img = (GlobalByte *)k.img;
 #pragma unroll
-    for (int m = 0; m < kGatherPerThread; ++m) {
-        if (m == kGatherPerThread - 1 && !has_last) break;
-        const int u = (int)(short)(uv[m] & 0xffff);
-        const int v = uv[m] >> 16;
-        int dx = mul_i24(mad_i24(k.c, u, -mul_i24(k.s, v)), k.sq);   // |dx|, |dy| < 2^30
-        int dy = mul_i24(mad_i24(k.s, u, mul_i24(k.c, v)), k.sq);
-        if (k.interior) {
-            const int base = k.cy * pitch + k.cx;
+    for (int m = 0; m < kFullSlots; ++m)
+        gather_orbit(k, img, sl.uv[m], true, g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
+    gather_orbit(k, img, sl.uv[4], tid < kSlot4Orbits, g[16], g[17], g[18], g[19]);
+    if (wave0 && tid < kSlot5Singles) g[20] = gather_single(k, img, sl.uv[5]);
+}
+
+__device__ __forceinline__ void write_orbit(uint8_t *lds, uint32_t raw, bool whole, uint32_t g0,
+                                            uint32_t g1, uint32_t g2, uint32_t g3)
+{
+    const uint32_t r0 = raw & 0xffffu, r1 = raw >> 16;
+    lds[r0] = (uint8_t)g0;
+    if (whole) {
+        lds[r1] = (uint8_t)g1;
+        lds[2 * kRawCentre - r0] = (uint8_t)g2;
+        lds[2 * kRawCentre - r1] = (uint8_t)g3;
+    }
+}
+
+// The gathered samples into the raw window.
+__device__ __forceinline__ void write_raw(uint8_t *lds, int tid, bool wave0, const Slots &sl,
+                                          const uint32_t (&g)[kSamples])
+{
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int off = __mul24(round_q22(dy), pitch) + round_q22(dx) + base;
-                g[4 * m + b] = img[(uint32_t)off];
-                dx += k.ca;
-                dy += k.sb;
-            }
-        } else {
+    for (int m = 0; m < kFullSlots; ++m)
+        write_orbit(lds, sl.raw[m], true, g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
+    write_orbit(lds, sl.raw[4], tid < kSlot4Orbits, g[16], g[17], g[18], g[19]);
+    if (wave0 && tid < kSlot5Singles) lds[sl.raw[5]] = (uint8_t)g[20];
+}
+
+// Copy unit e = 5 y + q: from raw bytes (y, 8 q .. 8 q + 15) build the
+// quadword q of row y of every copy (and of the edge copies when q = 4).
+__device__ __forceinline__ void copy_unit(uint8_t *lds, int e)
+{
+    const int y = e / kCopyQwords, q = e - kCopyQwords * y;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(lds + kRawBase + y * kRawStride + 8 * q);
+    const uint32_t d0 = src[0], d1 = src[1], d2 = src[2], d3 = src[3];
+    constexpr uint32_t m = 0x00ffffffu;
+    uint32_t lo[kCopies], hi[kCopies];
+    lo[0] = d0;
+    lo[1] = __builtin_amdgcn_alignbyte(d1, d0, 1);
+    lo[2] = __builtin_amdgcn_alignbyte(d1, d0, 2);
+    lo[3] = __builtin_amdgcn_alignbyte(d1, d0, 3);
+    lo[4] = d1;
+    lo[5] = __builtin_amdgcn_alignbyte(d2, d1, 1);
+    lo[6] = __builtin_amdgcn_alignbyte(d2, d1, 2);
+    lo[7] = __builtin_amdgcn_alignbyte(d2, d1, 3);
 #pragma unroll
-            for (int b = 0; b < 4; ++b) {
-                const int X = clamp_med3(k.cx + round_q22(dx), 0, width - 1);
-                const int Y = clamp_med3(k.cy + round_q22(dy), 0, height - 1);
-                g[4 * m + b] = img[(uint32_t)__mul24(Y, pitch) + (uint32_t)X];
-                dx += k.ca;
-                dy += k.sb;
-            }
-        }
+    for (int s = 0; s < 4; ++s) hi[s] = lo[s + 4] & m;
+    hi[4] = d2 & m;
+    hi[5] = __builtin_amdgcn_alignbyte(d3, d2, 1) & m;
+    hi[6] = __builtin_amdgcn_alignbyte(d3, d2, 2) & m;
+    hi[7] = __builtin_amdgcn_alignbyte(d3, d2, 3) & m;
+#pragma unroll
+    for (int s = 0; s < kCopies; ++s)
+        *reinterpret_cast<uint2 *>(lds + s * kCopyBytes + 8 * e) = make_uint2(lo[s], hi[s]);
+    if (q == kCopyQwords - 1) {
+        // Columns 40..46 and 41..47.
+        *reinterpret_cast<uint2 *>(lds + kEdgeBase + 8 * e) = make_uint2(d2, d3 & m);
+        *reinterpret_cast<uint2 *>(lds + kEdgeBase + 8 + 8 * e) =
+            make_uint2(__builtin_amdgcn_alignbyte(d3, d2, 1), d3 >> 8);
     }
 }
 
@@ -247,33 +399,33 @@ struct Rows {
     uint2 a[7], c[7], e[7];
 };
 
-__device__ __forceinline__ void load_rows(const uint8_t *winb, uint32_t oa, uint32_t o1, uint32_t o2,
+__device__ __forceinline__ void load_rows(const uint8_t *lds, uint32_t oa, uint32_t o1, uint32_t o2,
                                           Rows &r)
 {
 #pragma unroll
     for (int k = 0; k < 2 * kPatchR + 1; ++k) {
-        r.a[k] = *reinterpret_cast<const uint2 *>(winb + oa + kRowBytes * k);
-        r.c[k] = *reinterpret_cast<const uint2 *>(winb + o1 + kRowBytes * k);
-        r.e[k] = *reinterpret_cast<const uint2 *>(winb + o2 + kRowBytes * k);
+        r.a[k] = *reinterpret_cast<const uint2 *>(lds + oa + kCopyRowBytes * k);
+        r.c[k] = *reinterpret_cast<const uint2 *>(lds + o1 + kCopyRowBytes * k);
+        r.e[k] = *reinterpret_cast<const uint2 *>(lds + o2 + kCopyRowBytes * k);
     }
 }
 
 // Eq. 1 on one triplet: [||A - C1||^2 > ||A - C2||^2], via
-// ||A - Ck||^2 - sum A^2 = sum Ck^2 - 2 sum A Ck.
+// ||A - Ck||^2 - sum A^2 = sum Ck^2 - 2 sum A Ck.  The zero last byte of
+// every row quadword keeps the sums to the 7 x 7 patch.
 __device__ __forceinline__ bool triplet_bit(const Rows &r)
 {
     uint32_t ac1 = 0, ac2 = 0, q1 = 0, q2 = 0;
 #pragma unroll
     for (int k = 0; k < 2 * kPatchR + 1; ++k) {
-        const uint32_t c1 = r.c[k].y & 0x00ffffffu, e1 = r.e[k].y & 0x00ffffffu;
         ac1 = dot4(r.a[k].x, r.c[k].x, ac1);
-        ac1 = dot4(r.a[k].y, c1, ac1);
+        ac1 = dot4(r.a[k].y, r.c[k].y, ac1);
         ac2 = dot4(r.a[k].x, r.e[k].x, ac2);
-        ac2 = dot4(r.a[k].y, e1, ac2);
+        ac2 = dot4(r.a[k].y, r.e[k].y, ac2);
         q1 = dot4(r.c[k].x, r.c[k].x, q1);
-        q1 = dot4(c1, c1, q1);
+        q1 = dot4(r.c[k].y, r.c[k].y, q1);
         q2 = dot4(r.e[k].x, r.e[k].x, q2);
-        q2 = dot4(e1, e1, q2);
+        q2 = dot4(r.e[k].y, r.e[k].y, q2);
     }
     return (int)(q1 - 2u * ac1) > (int)(q2 - 2u * ac2);
 }
@@ -284,13 +436,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off, uint32_t *__restrict__ desc,
     uint32_t *__restrict__ flags)
 {
-    __shared__ __attribute__((aligned(16))) uint32_t win[kWinLdsBytes / 4];
-    const uint8_t *winb = reinterpret_cast<const uint8_t *>(win);
+    __shared__ __attribute__((aligned(16))) uint8_t lds[kWinLdsBytes];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool has_last = wave == 0;          // window dwords 512..575 belong to wavefront 0
+    const bool wave0 = wave == 0;
 
     // Wavefront w evaluates rounds 4 w .. 4 w + 3: triplet t = 64 r + lane in round r.
     uint32_t off_a1[kRoundsPerWave], off_2[kRoundsPerWave];
@@ -307,13 +458,12 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     int64_t p = blockIdx.x;
     if (p >= n) return;
     const int64_t stride = gridDim.x;
-    int uv[kGatherPerThread];
-    thread_coords(tid, uv);
+    const Slots sl = thread_slots(tid);
     uint32_t g[kSamples];
     KeypointBatch batch = prepare_batch<kTable>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
     Keypoint cur = batch_get(batch, 0, &bad_image);
-    if (cur.ok) issue_gather(cur, has_last, uv, g);
+    if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
 
     for (int i = 0; p < n; ++i, p += stride) {
         const bool compute = cur.ok;
@@ -321,43 +471,20 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
             if (tid < kWords) desc[p * kWords + tid] = 0u;
             if (tid == 0) atomicOr(flags, bad_image ? kFlagBadImage : kFlagBadKeypoint);
         } else {
-            // Copy 0: the window itself, row pitch 48 bytes.
-            uint32_t w[kGatherPerThread];
-#pragma unroll
-            for (int m = 0; m < kGatherPerThread; ++m)
-                w[m] = g[4 * m] | (g[4 * m + 1] << 8) | (g[4 * m + 2] << 16) | (g[4 * m + 3] << 24);
-            __syncthreads();   // the previous descriptor's reads of `win` are done
-#pragma unroll
-            for (int m = 0; m < kGatherPerThread; ++m) {
-                if (m == kGatherPerThread - 1 && !has_last) break;
-                win[tid + kThreads * m] = w[m];
-            }
-            __syncthreads();
-            // Copies 1..7: copy s holds at (row r, byte x) the window byte
-            // (r, x + s).  Bytes past column 47 of a row are only ever read
-            // masked; past the last row they are zero.
-#pragma unroll
-            for (int m = 0; m < kGatherPerThread; ++m) {
-                if (m == kGatherPerThread - 1 && !has_last) break;
-                const int d = tid + kThreads * m;
-                const uint32_t n1 = d + 1 < kGatherDwords ? win[d + 1] : 0u;
-                const uint32_t n2 = d + 2 < kGatherDwords ? win[d + 2] : 0u;
-                win[1 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n1, w[m], 1);
-                win[2 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n1, w[m], 2);
-                win[3 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n1, w[m], 3);
-                win[4 * (kCopyBytes / 4) + d] = n1;
-                win[5 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n2, n1, 1);
-                win[6 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n2, n1, 2);
-                win[7 * (kCopyBytes / 4) + d] = __builtin_amdgcn_alignbyte(n2, n1, 3);
-            }
-            __syncthreads();
+            // The raw window was last read by the previous descriptor's copy
+            // pass, which ended before that descriptor's second barrier.
+            write_raw(lds, tid, wave0, sl, g);
+            __syncthreads();   // raw window complete; the previous triplet reads are done
+            copy_unit(lds, tid);
+            if (tid < kCopyUnits - kThreads) copy_unit(lds, tid + kThreads);
+            __syncthreads();   // copies complete
         }
 
         // Start the next keypoint's gather; it completes during the arithmetic below.
         const int j = (i + 1) & 63;
         if (j == 0) batch = prepare_batch<kTable>(kps, n, p + stride, stride, lane, rot, src);
         cur = batch_get(batch, j, &bad_image);
-        if (cur.ok) issue_gather(cur, has_last, uv, g);
+        if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
         if (!compute) continue;
 
         // Eq. 1 for this wavefront's 256 triplets.
@@ -365,7 +492,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 #pragma unroll
         for (int r = 0; r < kRoundsPerWave; ++r) {
             Rows rows;
-            load_rows(winb, off_a1[r] & 0xffffu, off_a1[r] >> 16, off_2[r], rows);
+            load_rows(lds, off_a1[r] & 0xffffu, off_a1[r] >> 16, off_2[r], rows);
             const uint64_t bits = __ballot(triplet_bit(rows));
             if (lane == 2 * r) out_word = (uint32_t)bits;
             if (lane == 2 * r + 1) out_word = (uint32_t)(bits >> 32);

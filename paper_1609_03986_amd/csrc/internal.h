@@ -14,14 +14,27 @@ constexpr int kTriplets = 512;
 constexpr int kWords = 16;
 constexpr int kBins = 4096;
 
-// Extraction LDS layout, per wavefront: eight byte-shifted copies of the
-// 48 x 48 u8 window.  Copy s holds, at byte (r * kRowBytes + x), window byte
-// (r, x + s).  Any 7-byte patch row starting at column c0 is then the first
-// 7 bytes of the 8-byte-aligned quadword at copy (c0 & 7), column c0 - (c0 & 7).
-constexpr int kShiftCopies = 8;
-constexpr int kRowBytes = 48;
-constexpr int kCopyBytes = kWin * kRowBytes;               // 2304
-constexpr int kWinLdsBytes = kShiftCopies * kCopyBytes;    // 18432 per workgroup
+// Extraction LDS layout, per workgroup.
+//  * Copies s = 0..7: copy s holds, for every window row y and quadword
+//    q = 0..4, the 7 window bytes (y, 8 q + s .. 8 q + s + 6) followed by a
+//    zero byte, at byte s * kCopyBytes + y * kCopyRowBytes + 8 q.  A 7-byte
+//    patch row starting at column x <= 39 is then one 8-byte-aligned
+//    quadword whose last byte is zero.
+//  * Edge copies for x = 40 and 41 (patch centres in columns 43, 44): the
+//    quadword of row y sits at kEdgeBase + y * kCopyRowBytes + 32 + 8 (x - 40).
+//    The two interleave without overlap, so all patch rows share the row
+//    stride kCopyRowBytes.
+//  * The plain window, 48 rows of kRawStride bytes (13 dwords per row, so
+//    the lanes of a column-wise byte write fall in distinct banks).
+constexpr int kCopies = 8;
+constexpr int kCopyQwords = 5;
+constexpr int kCopyRowBytes = 8 * kCopyQwords;                     // 40
+constexpr int kCopyBytes = kWin * kCopyRowBytes;                   // 1920
+constexpr int kEdgeBase = kCopies * kCopyBytes;                    // 15360
+constexpr int kEdgeBytes = kCopyBytes + 8;                         // 1928
+constexpr int kRawBase = (kEdgeBase + kEdgeBytes + 15) / 16 * 16;  // 17296
+constexpr int kRawStride = 52;
+constexpr int kWinLdsBytes = kRawBase + kWin * kRawStride;         // 19792 per workgroup
 constexpr int kExtractWaves = 2;                           // wavefronts per workgroup
 constexpr int kLdsPerCu = 160 * 1024;                      // gfx950
 
@@ -68,10 +81,22 @@ struct KnnPlan {
     int nsplit;
 };
 
-hipError_t launch_knn_mfma(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
-                           uint64_t *partial, hipStream_t stream);
-hipError_t launch_knn_popcount(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
-                               uint64_t *partial, hipStream_t stream);
+// Single-pair matching over train splits.  With one split the results are
+// written directly; otherwise each (split, query) writes its two best as
+// partials and launch_knn_merge reduces them.
+struct KnnSplitArgs {
+    const uint32_t *query, *train;
+    KnnPlan plan;
+    uint64_t *partial;
+    int k;
+    float ratio;
+    int32_t *idx, *dist;
+    uint8_t *accept;
+};
+
+hipError_t launch_knn_split(const KnnSplitArgs &a, bool mfma, hipStream_t stream);
+hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream);
+
 // Layout-compatible with latch_pair of the C ABI.
 struct PairEntry {
     int64_t query_first, nq, train_first, nt, out_first;
@@ -109,8 +134,5 @@ struct BatchArgs {
 };
 
 hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream);
-
-hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k, float ratio,
-                            int32_t *idx, int32_t *dist, uint8_t *accept, hipStream_t stream);
 
 }  // namespace latch

@@ -37,10 +37,11 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
 }
 
 // Four bits -> four bytes of value 0/1 (bit e of nib -> byte e).  The four
-// shifted copies of nib occupy disjoint bit ranges, so the product has no carries.
+// shifted copies of nib occupy disjoint bit ranges, so the product has no
+// carries; nib < 16 and the constant < 2^24 make it a full-rate 24-bit multiply.
 __device__ __forceinline__ uint32_t spread_nibble(uint32_t nib)
 {
-    return (nib * 0x00204081u) & 0x01010101u;
+    return __umul24(nib, 0x00204081u) & 0x01010101u;
 }
 
 // 16 bits -> 16 bytes of value 0/1, byte m = bit m.
@@ -89,6 +90,7 @@ constexpr int kMfmaThreads = kMfmaWaves * 64;
 constexpr int kQueryBlocks = 2;                        // 32-query blocks per wavefront
 constexpr int kQueriesPerWave = 32 * kQueryBlocks;
 constexpr int kQueriesPerGroup = kMfmaWaves * kQueriesPerWave;
+static_assert(kQueriesPerGroup == 256, "query groups of 256 in every matcher");
 constexpr int kTileVec = kTileBytes / 16;              // 16-byte fragments per tile (1024)
 static_assert(kMfmaThreads == 8 * kTileRows, "staging: 8 threads per tile row");
 
@@ -189,8 +191,13 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     const int t_begin = split * tiles_per_split;
     const int t_end = min(ntiles_all, t_begin + tiles_per_split);
 
-    uint2 ld = make_uint2(0, 0);
-    if (t_begin < t_end) ld = load_tile(train, nt, t_begin, tid);
+    // Packed train tiles in flight: ld0 is staged next, ld1 and ld2 follow.
+    // A tile's MFMAs take about 1000 cycles, less than an L2 miss, so loads
+    // are issued three tiles ahead of their use.
+    uint2 ld0 = make_uint2(0, 0), ld1 = ld0, ld2 = ld0;
+    if (t_begin < t_end) ld0 = load_tile(train, nt, t_begin, tid);
+    if (t_begin + 1 < t_end) ld1 = load_tile(train, nt, t_begin + 1, tid);
+    if (t_begin + 2 < t_end) ld2 = load_tile(train, nt, t_begin + 2, tid);
 
     // Resident query fragments and query popcounts.
     v4i bq[kQueryBlocks][16];
@@ -213,13 +220,14 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     for (int qb = 0; qb < kQueryBlocks; ++qb) k1[qb] = k2[qb] = 0u;
 
     __syncthreads();       // the staging buffer may still be read by a previous item
-    if (t_begin < t_end) stage_tile(ld, tid, tbuf[0]);
+    if (t_begin < t_end) stage_tile(ld0, tid, tbuf[0]);
     __syncthreads();
 
     for (int tile = t_begin; tile < t_end; ++tile) {
         const int buf = (tile - t_begin) & 1;
         const bool more = tile + 1 < t_end;
-        if (more) ld = load_tile(train, nt, tile + 1, tid);     // lands during the MFMAs below
+        uint2 ld3 = make_uint2(0, 0);
+        if (tile + 3 < t_end) ld3 = load_tile(train, nt, tile + 3, tid);
 
         v16i acc[kQueryBlocks];
 #pragma unroll
@@ -260,7 +268,9 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
             }
         }
 
-        if (more) stage_tile(ld, tid, tbuf[buf ^ 1]);
+        if (more) stage_tile(ld1, tid, tbuf[buf ^ 1]);
+        ld1 = ld2;
+        ld2 = ld3;
         __syncthreads();
     }
 
@@ -290,15 +300,6 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
             store_pair(r[0], r[1], nq, nt, split, out, qn);
         }
     }
-}
-
-__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
-knn_mfma_kernel(const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train,
-                int nt, int split_rows, uint64_t *__restrict__ partial)
-{
-    __shared__ v4i tbuf[2][kTileVec];
-    const ItemOut out{partial, nullptr, nullptr, nullptr, 2, 0.f};
-    mfma_item(query, nq, train, nt, blockIdx.x, blockIdx.y, split_rows, out, tbuf);
 }
 
 // ---------------------------------------------------------------------------
@@ -342,25 +343,14 @@ __device__ __forceinline__ void popcount_item(const uint32_t *__restrict__ query
     }
 }
 
-__global__ __launch_bounds__(256) void knn_popcount_kernel(
-    const uint32_t *__restrict__ query, int nq, const uint32_t *__restrict__ train, int nt,
-    int split_rows, uint64_t *__restrict__ partial)
-{
-    const ItemOut out{partial, nullptr, nullptr, nullptr, 2, 0.f};
-    popcount_item(query, nq, train, nt, blockIdx.x, blockIdx.y, split_rows, out);
-}
-
 // ---------------------------------------------------------------------------
 // Merge per-split partials (64-bit keys: distance << 32 | global index, so the
 // integer order is the lexicographic one) and apply the ratio test exactly:
 // a float32 ratio times an integer <= 512 is exact in double.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void knn_merge_kernel(
-    const uint64_t *__restrict__ partial, int nq, int nsplit, int nt, int k, float ratio,
-    int32_t *__restrict__ idx, int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
+__device__ __forceinline__ void merge_query(const uint64_t *__restrict__ partial, int nq, int nsplit,
+                                            int nt, const ItemOut &out, int q)
 {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= nq) return;
     uint64_t b1 = kNoNeighbour, b2 = kNoNeighbour;
     // Eight splits' loads in flight at a time, then a branch-free top-2 update.
     for (int s0 = 0; s0 < nsplit; s0 += 8) {
@@ -378,8 +368,50 @@ __global__ __launch_bounds__(256) void knn_merge_kernel(
             b1 = min(b1, v[i]);
         }
     }
-    const ItemOut out{nullptr, idx, dist, accept, k, ratio};
     store_final(b1, b2, nt, out, q);
+}
+
+// Arguments of the split matchers.  nsplit == 1: results go straight to
+// idx / dist / accept; otherwise per-(split, query) partials for the merge
+// kernel.
+struct SplitArgs {
+    const uint32_t *query;
+    const uint32_t *train;
+    int nq, nt, split_rows, nsplit;
+    uint64_t *partial;
+    int k;
+    float ratio;
+    int32_t *idx, *dist;
+    uint8_t *accept;
+};
+
+__global__ __launch_bounds__(256) void knn_merge_kernel(const uint64_t *__restrict__ partial, int nq,
+                                                        int nsplit, int nt, int k, float ratio,
+                                                        int32_t *__restrict__ idx,
+                                                        int32_t *__restrict__ dist,
+                                                        uint8_t *__restrict__ accept)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    merge_query(partial, nq, nsplit, nt, ItemOut{nullptr, idx, dist, accept, k, ratio}, q);
+}
+
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_mfma_kernel(SplitArgs a)
+{
+    __shared__ v4i tbuf[2][kTileVec];
+    const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
+    const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
+    mfma_item(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
+              a.nsplit == 1 ? direct : part, tbuf);
+}
+
+__global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
+{
+    const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
+    const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
+    popcount_item(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
+                  a.nsplit == 1 ? direct : part);
 }
 
 // ---------------------------------------------------------------------------
@@ -524,32 +556,26 @@ __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
 
 }  // namespace
 
-hipError_t launch_knn_mfma(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
-                           uint64_t *partial, hipStream_t stream)
+hipError_t launch_knn_split(const KnnSplitArgs &a, bool mfma, hipStream_t stream)
 {
-    const int64_t qblocks = (plan.nq + kQueriesPerGroup - 1) / kQueriesPerGroup;
-    hipLaunchKernelGGL(knn_mfma_kernel, dim3((unsigned)qblocks, (unsigned)plan.nsplit),
-                       dim3(kMfmaThreads), 0, stream, query, (int)plan.nq, train, (int)plan.nt,
-                       (int)plan.split_rows, partial);
+    const SplitArgs k{a.query, a.train, (int)a.plan.nq, (int)a.plan.nt, (int)a.plan.split_rows,
+                      a.plan.nsplit, a.partial, a.k, a.ratio, a.idx, a.dist, a.accept};
+    const int64_t qgroups = (a.plan.nq + 255) / 256;
+    if (mfma)
+        hipLaunchKernelGGL(knn_mfma_kernel, dim3((unsigned)qgroups, (unsigned)a.plan.nsplit),
+                           dim3(kMfmaThreads), 0, stream, k);
+    else
+        hipLaunchKernelGGL(knn_popcount_kernel, dim3((unsigned)qgroups, (unsigned)a.plan.nsplit),
+                           dim3(256), 0, stream, k);
     return hipGetLastError();
 }
 
-hipError_t launch_knn_popcount(const uint32_t *query, const uint32_t *train, const KnnPlan &plan,
-                               uint64_t *partial, hipStream_t stream)
+hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream)
 {
-    const int64_t qblocks = (plan.nq + 255) / 256;
-    hipLaunchKernelGGL(knn_popcount_kernel, dim3((unsigned)qblocks, (unsigned)plan.nsplit),
-                       dim3(256), 0, stream, query, (int)plan.nq, train, (int)plan.nt,
-                       (int)plan.split_rows, partial);
-    return hipGetLastError();
-}
-
-hipError_t launch_knn_merge(const uint64_t *partial, const KnnPlan &plan, int k, float ratio,
-                            int32_t *idx, int32_t *dist, uint8_t *accept, hipStream_t stream)
-{
-    const int64_t blocks = (plan.nq + 255) / 256;
-    hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, partial,
-                       (int)plan.nq, plan.nsplit, (int)plan.nt, k, ratio, idx, dist, accept);
+    const int64_t blocks = (a.plan.nq + 255) / 256;
+    hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a.partial,
+                       (int)a.plan.nq, a.plan.nsplit, (int)a.plan.nt, a.k, a.ratio, a.idx, a.dist,
+                       a.accept);
     return hipGetLastError();
 }
 

@@ -74,13 +74,14 @@ void rotation_table(int16_t *c, int16_t *s)
     }
 }
 
-// LDS byte offset of the top-left byte of the 7 x 7 patch centred on (r, c),
-// in the byte-shifted copy that makes its rows 8-byte aligned.
+// LDS byte offset of the top-left byte of the 7 x 7 patch centred on (r, c):
+// the quadword of the copy that holds its first row (see internal.h).
 uint32_t patch_offset(int r, int c)
 {
-    const int c0 = c - kPatchR;
-    const int shift = c0 & (kShiftCopies - 1);
-    return (uint32_t)(shift * kCopyBytes + (r - kPatchR) * kRowBytes + (c0 - shift));
+    const int x = c - kPatchR, y = r - kPatchR;
+    if (x < 8 * kCopyQwords)
+        return (uint32_t)((x & 7) * kCopyBytes + y * kCopyRowBytes + 8 * (x >> 3));
+    return (uint32_t)(kEdgeBase + 8 * (x - 8 * kCopyQwords) + y * kCopyRowBytes + 8 * (kCopyQwords - 1));
 }
 
 int ensure_workspace(latch_handle h, size_t need)
@@ -393,28 +394,30 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
         return fail(h, LATCH_EINVAL, "null buffer");
     if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
 
-    const KnnPlan plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
-    const size_t partial_bytes = align_up((size_t)plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
-    int rc = ensure_workspace(h, partial_bytes);
-    if (rc != LATCH_OK) return rc;
-    uint64_t *partial = reinterpret_cast<uint64_t *>(h->ws);
-
-    hipError_t e;
-    if (path == LATCH_PATH_MFMA) {
-        e = timed_launch(h, "knn_mfma", stream, [&] {
-            return launch_knn_mfma(query_dev, train_dev, plan, partial, stream);
-        });
-        if (e != hipSuccess) return hip_fail(h, e, "mfma launch");
-    } else {
-        e = timed_launch(h, "knn_popcount", stream, [&] {
-            return launch_knn_popcount(query_dev, train_dev, plan, partial, stream);
-        });
-        if (e != hipSuccess) return hip_fail(h, e, "popcount launch");
+    KnnSplitArgs a;
+    a.query = query_dev;
+    a.train = train_dev;
+    a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
+    a.partial = nullptr;
+    a.k = k;
+    a.ratio = ratio;
+    a.idx = idx_dev;
+    a.dist = dist_dev;
+    a.accept = accept_dev;
+    if (a.plan.nsplit > 1) {
+        const size_t partial_bytes = align_up((size_t)a.plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
+        const int rc = ensure_workspace(h, partial_bytes);
+        if (rc != LATCH_OK) return rc;
+        a.partial = reinterpret_cast<uint64_t *>(h->ws);
     }
-    e = timed_launch(h, "knn_merge", stream, [&] {
-        return launch_knn_merge(partial, plan, k, ratio, idx_dev, dist_dev, accept_dev, stream);
-    });
-    if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    const bool mfma = path == LATCH_PATH_MFMA;
+    hipError_t e = timed_launch(h, mfma ? "knn_mfma" : "knn_popcount", stream,
+                                [&] { return launch_knn_split(a, mfma, stream); });
+    if (e != hipSuccess) return hip_fail(h, e, mfma ? "mfma launch" : "popcount launch");
+    if (a.plan.nsplit > 1) {
+        e = timed_launch(h, "knn_merge", stream, [&] { return launch_knn_merge(a, stream); });
+        if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    }
     return LATCH_OK;
 }
 

@@ -245,7 +245,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="Serve extract + match requests against a "
                                              "device-resident database; print one JSON line per rate.")
     ap.add_argument("--qps", type=float, nargs="+", default=[50, 200, 800])
-    ap.add_argument("--requests", type=int, default=200)
+    ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--db-rows", type=int, default=1_000_000)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--hbm-budget-gb", type=float, default=8.0)

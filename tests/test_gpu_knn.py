@@ -148,3 +148,14 @@ def test_bad_arguments_raise(torch_cuda, lat):
         assert e.value.code == code
     idx, dist, acc = lat.knn(q[:0], q)          # nq = 0 is a no-op
     assert idx.shape == (0, 2)
+
+
+def test_split_merge_repeated_calls(torch_cuda, lat):
+    """The split merge's per-group counters return to zero after every call:
+    alternating shapes with many train splits on one handle stay exact."""
+    g = np.random.default_rng(77)
+    shapes = [(600, 50000), (2000, 9000), (600, 50000), (257, 123457), (2000, 9000)]
+    for nq, nt in shapes:
+        Q = synth.random_descriptors(g, nq)
+        T = synth.random_descriptors(g, nt)
+        check(torch_cuda, lat, Q, T, k=2)
