@@ -1,6 +1,7 @@
 """Autotuner for the matcher: picks, per (query count, train count) size
-bucket, the faster of the int8-MFMA and popcount paths, the path for
-batched matching, and the split planner's workgroups-per-CU target.  It
+bucket, the fastest of the int8-MFMA, MXFP4-MFMA and popcount paths, the
+path for batched matching (int8 MFMA or popcount), and the split planner's
+workgroups-per-CU target.  It
 measures the library's own kernels (HIP events recorded by the library on
 its launch stream) on random descriptors and caches the result per device
 and library version.
@@ -16,7 +17,7 @@ import sys
 import numpy as np
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "latch_gfx950", "autotune.json")
-MFMA, POPCOUNT = 1, 2
+MFMA, POPCOUNT, FP4 = 1, 2, 3
 
 
 def bucket_shape(b):
@@ -57,7 +58,7 @@ def _time_knn(lat, q, t, path, reps):
         lat.knn(q, t, path=path)
     torch.cuda.synchronize()
     total = 0.0
-    for name in ("knn_mfma", "knn_popcount", "knn_merge"):
+    for name in ("knn_mfma", "knn_fp4", "knn_popcount", "knn_merge"):
         n, ms = lat.timing_read(name)
         total += ms
     lat.timing(False)
@@ -82,25 +83,27 @@ def tune(lat, buckets=None, reps=5, seed=0, log=None):
         nq, nt = min(bucket_shape(qb), cap), min(bucket_shape(tb), cap)
         q, t = pool[:nq], pool[rows - nt:]
         ts = {MFMA: _time_knn(lat, q, t, "mfma", reps),
+              FP4: _time_knn(lat, q, t, "fp4", reps),
               POPCOUNT: _time_knn(lat, q, t, "popcount", reps)}
         measured[(qb, tb)] = choose(ts)
         if log:
-            log("bucket (%d, %d) nq=%d nt=%d: mfma %.1f us, popcount %.1f us" %
-                (qb, tb, nq, nt, ts[MFMA] * 1e6, ts[POPCOUNT] * 1e6))
+            log("bucket (%d, %d) nq=%d nt=%d: mfma %.1f us, fp4 %.1f us, popcount %.1f us" %
+                (qb, tb, nq, nt, ts[MFMA] * 1e6, ts[FP4] * 1e6, ts[POPCOUNT] * 1e6))
     tuning = dict(base)
     tuning["path"] = fill_table(measured)
-    # Split planner target on the 10,000 x 10,000 shape.
+    # Split planner target on the 10,000 x 10,000 shape, for the faster MFMA path there.
     q, t = pool[:10000], pool[rows - 10000:] if rows >= 20000 else pool[:10000]
+    mfma_path = "fp4" if tuning["path"][6][6] == FP4 else "mfma"
     targets = {}
     for w in (1, 2, 3, 4):
         trial = dict(tuning, mfma_groups_per_cu=w)
         lat.set_tuning(Tuning.from_dict(trial))
-        targets[w] = _time_knn(lat, q, t, "mfma", reps)
+        targets[w] = _time_knn(lat, q, t, mfma_path, reps)
     tuning["mfma_groups_per_cu"] = choose(targets)
     if log:
         log("mfma workgroups per CU: %s -> %d" %
             ({w: round(v * 1e6, 1) for w, v in targets.items()}, tuning["mfma_groups_per_cu"]))
-    tuning["batch_path"] = tuning["path"][6][6]
+    tuning["batch_path"] = POPCOUNT if tuning["path"][6][6] == POPCOUNT else MFMA
     lat.set_tuning(Tuning.from_dict(tuning))
     return tuning
 

@@ -22,7 +22,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblatch.so")
 
 LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE = 0, -1, -2, -3, -4
-PATHS = {"auto": 0, "mfma": 1, "popcount": 2}
+PATHS = {"auto": 0, "mfma": 1, "popcount": 2, "fp4": 3}
 FLAG_BAD_KEYPOINT = 1
 FLAG_BAD_IMAGE = 2
 FLAG_BAD_PAIR = 4
@@ -37,7 +37,8 @@ EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batc
            "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
-KERNELS = ("extract", "knn_mfma", "knn_popcount", "knn_merge", "knn_batch_mfma", "knn_batch_popcount")
+KERNELS = ("extract", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge", "knn_batch_mfma",
+           "knn_batch_popcount")
 
 
 class LatchError(RuntimeError):

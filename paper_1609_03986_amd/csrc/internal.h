@@ -94,7 +94,10 @@ struct KnnSplitArgs {
     uint8_t *accept;
 };
 
-hipError_t launch_knn_split(const KnnSplitArgs &a, bool mfma, hipStream_t stream);
+enum class SplitKernel { kMfmaI8, kMfmaFp4, kPopcount };
+constexpr int64_t kFp4MaxSplitRows = 1 << 14;    // MXFP4 keys hold a 14-bit split-local index
+
+hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_t stream);
 hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream);
 
 // Layout-compatible with latch_pair of the C ABI.

@@ -303,6 +303,212 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
 }
 
 // ---------------------------------------------------------------------------
+// MXFP4 matcher.  Same tiling as the int8 path, on the block-scaled FP4
+// matrix instruction v_mfma_scale_f32_32x32x64_f8f6f4 (K = 64 per
+// instruction, twice the int8 rate on gfx950).
+//
+// Operands.  FP4 (e2m1) holds 0 (0x0), +1 (0x2) and -1 (0xa) exactly.
+// Train bits enter as 0 / +1 with block scale 2^0, query bits as
+// +1 / -1 (set / clear) with block scale 2^14, so each product is 0 or
+// +-2^14 and the f32 sum over K = 512 is 2^14 s with s = |a| - Hamming(a, b)
+// as in the int8 path, exact (|2^14 s| <= 2^23).
+//
+// Keys.  For tile row m the accumulator starts at c_m = 2^14 - 1 - m, so it
+// ends at 2^14 s + c_m; the running top-2 of a lane is kept in the frame of
+// the current tile and moved up by 32 when the next tile starts, so a key
+// from split-local row jl = 32 t + m ends as 2^14 s + 2^14 - 1 - jl + 32 T
+// after T tiles (T < 512): integers below 2^24 in magnitude, exact in f32.
+// For a fixed query the largest key is the smallest (distance, index).  Rows
+// past nt (last tile only) start at -2^25 instead, below every real key,
+// which also marks "no neighbour".  Top-2 selection is one v_max_f32 and
+// one v_med3_f32 per pair.
+//
+// Fragment order.  Step s (0..7), lane l: the 32 elements of row l % 32 at
+// K = 64 s + 32 (l / 32) + e are packed word 2 s + l / 32 of that row, bit e
+// -> nibble e (16 bytes).  Queries use the same map.  Bytes expand to FP4
+// through a 256-entry table in LDS (byte -> 8 nibbles).
+// ---------------------------------------------------------------------------
+typedef float v16f __attribute__((ext_vector_type(16)));
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+constexpr int kFp4Steps = 8;                          // K = 512 = 8 x 64
+constexpr int kFp4TileVec = kFp4Steps * 64;           // 16-byte fragments per tile (512)
+constexpr int kFp4ScaleTrain = 127;                   // E8M0 2^0
+constexpr int kFp4ScaleQuery = 127 + 14;              // E8M0 2^14
+constexpr float kFp4None = -33554432.0f;              // -2^25
+
+// Byte -> 8 FP4 nibbles (bit e -> nibble e): `one` for a set bit, `zero` for a clear one.
+__device__ __forceinline__ uint32_t fp4_byte(uint32_t byte, uint32_t one, uint32_t zero)
+{
+    uint32_t r = 0;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r |= ((byte >> e) & 1u ? one : zero) << (4 * e);
+    return r;
+}
+
+__device__ __forceinline__ uint4 fp4_word(uint32_t w, const uint32_t *__restrict__ lut)
+{
+    return make_uint4(lut[w & 0xffu], lut[(w >> 8) & 0xffu], lut[(w >> 16) & 0xffu], lut[w >> 24]);
+}
+
+// Maximum of two finite floats as one v_max_f32 (the IEEE-mode fmaxf adds
+// a NaN-quieting instruction per operand; keys are never NaN).
+__device__ __forceinline__ float max_key(float a, float b)
+{
+    float r;
+    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ v8i fp4_operand(uint4 f)
+{
+    v8i r = {};
+    r[0] = (int)f.x;
+    r[1] = (int)f.y;
+    r[2] = (int)f.z;
+    r[3] = (int)f.w;
+    return r;
+}
+
+// Staging role of a thread: tile row tid % 32, packed words 2 (tid / 32) and
+// 2 (tid / 32) + 1, i.e. step tid / 32, both lane halves.
+__device__ __forceinline__ void stage_tile_fp4(uint2 w, int tid, const uint32_t *__restrict__ lut,
+                                               uint4 *__restrict__ buf)
+{
+    const int r = tid & 31;
+    const int s = tid >> 5;
+    buf[s * 64 + r] = fp4_word(w.x, lut);
+    buf[s * 64 + 32 + r] = fp4_word(w.y, lut);
+}
+
+__device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int nq,
+                                         const uint32_t *__restrict__ train, int nt, int qgroup,
+                                         int split, int split_rows, const ItemOut &out,
+                                         uint4 (*tbuf)[kFp4TileVec], const uint32_t *lut_train,
+                                         const uint32_t *lut_query)
+{
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int half = lane >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int qbase = qgroup * kQueriesPerGroup + wave * kQueriesPerWave;
+
+    const int ntiles_all = (nt + kTileRows - 1) / kTileRows;
+    const int tiles_per_split = split_rows / kTileRows;
+    const int t_begin = split * tiles_per_split;
+    const int t_end = min(ntiles_all, t_begin + tiles_per_split);
+
+    uint2 ld0 = make_uint2(0, 0), ld1 = ld0, ld2 = ld0;
+    if (t_begin < t_end) ld0 = load_tile(train, nt, t_begin, tid);
+    if (t_begin + 1 < t_end) ld1 = load_tile(train, nt, t_begin + 1, tid);
+    if (t_begin + 2 < t_end) ld2 = load_tile(train, nt, t_begin + 2, tid);
+
+    // Resident query fragments (+-1) and query popcounts.
+    uint4 bq[kQueryBlocks][kFp4Steps];
+    int na[kQueryBlocks];
+#pragma unroll
+    for (int qb = 0; qb < kQueryBlocks; ++qb) {
+        const int qn = qbase + 32 * qb + (lane & 31);
+        int pc = 0;
+#pragma unroll
+        for (int s = 0; s < kFp4Steps; ++s) {
+            const uint32_t w0 = qn < nq ? query[(size_t)qn * kWords + 2 * s] : 0u;
+            const uint32_t w1 = qn < nq ? query[(size_t)qn * kWords + 2 * s + 1] : 0u;
+            pc += __popc(w0) + __popc(w1);
+            bq[qb][s] = fp4_word(half ? w1 : w0, lut_query);
+        }
+        na[qb] = pc;
+    }
+
+    float k1[kQueryBlocks], k2[kQueryBlocks];
+#pragma unroll
+    for (int qb = 0; qb < kQueryBlocks; ++qb) k1[qb] = k2[qb] = kFp4None;
+
+    // Accumulator start values c_m; register r = 4 g + e holds tile row
+    // m = 8 g + 4 half + e.
+    v16f c0;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c0[r] = (float)((1 << 14) - 1 - (8 * (r >> 2) + 4 * half + (r & 3)));
+
+    if (t_begin < t_end) stage_tile_fp4(ld0, tid, lut_train, tbuf[0]);
+    __syncthreads();
+
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        const int buf = (tile - t_begin) & 1;
+        const bool more = tile + 1 < t_end;
+        uint2 ld3 = make_uint2(0, 0);
+        if (tile + 3 < t_end) ld3 = load_tile(train, nt, tile + 3, tid);
+
+        v16f acc[kQueryBlocks];
+#pragma unroll
+        for (int s = 0; s < kFp4Steps; ++s) {
+            const v8i a = fp4_operand(tbuf[buf][s * 64 + lane]);
+#pragma unroll
+            for (int qb = 0; qb < kQueryBlocks; ++qb)
+                acc[qb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    a, fp4_operand(bq[qb][s]), s == 0 ? c0 : acc[qb], 4, 4, 0, kFp4ScaleTrain, 0,
+                    kFp4ScaleQuery);
+        }
+        const int valid_rows = nt - tile * kTileRows;        // < 32 only in the last tile
+        if (valid_rows < kTileRows) {
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                if (8 * (r >> 2) + 4 * half + (r & 3) >= valid_rows)
+#pragma unroll
+                    for (int qb = 0; qb < kQueryBlocks; ++qb) acc[qb][r] = kFp4None;
+        }
+        // Move the running top-2 into this tile's frame, then update it.
+#pragma unroll
+        for (int qb = 0; qb < kQueryBlocks; ++qb) {
+            if (tile != t_begin) {
+                k1[qb] += 32.0f;
+                k2[qb] += 32.0f;
+            }
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const float key = acc[qb][r];
+                k2[qb] = __builtin_amdgcn_fmed3f(k1[qb], k2[qb], key);
+                k1[qb] = max_key(k1[qb], key);
+            }
+        }
+
+        if (more) stage_tile_fp4(ld1, tid, lut_train, tbuf[buf ^ 1]);
+        ld1 = ld2;
+        ld2 = ld3;
+        __syncthreads();
+    }
+
+    // Merge the two row halves and decode
+    // key = 2^14 (|a| - d) + 2^14 - 1 - jl + 32 (tiles - 1).
+    const int shift = 32 * max(t_end - t_begin - 1, 0);
+#pragma unroll
+    for (int qb = 0; qb < kQueryBlocks; ++qb) {
+        const float o1 = __shfl_xor(k1[qb], 32);
+        const float o2 = __shfl_xor(k2[qb], 32);
+        const float b1 = fmaxf(k1[qb], o1);
+        const float b2 = fmaxf(fminf(k1[qb], o1), fmaxf(k2[qb], o2));
+        const int qn = qbase + 32 * qb + (lane & 31);
+        if (half == 0 && qn < nq) {
+            uint64_t r[2];
+            const float kk[2] = {b1, b2};
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                if (kk[e] < -16777216.0f) {                  // a row past nt, or none
+                    r[e] = kNoNeighbour;
+                } else {
+                    const int key = (int)kk[e] - shift;
+                    const uint32_t d = (uint32_t)(na[qb] - (key >> 14));
+                    const uint32_t j = (uint32_t)split * (uint32_t)split_rows +
+                                       (uint32_t)((1 << 14) - 1 - (key & 0x3fff));
+                    r[e] = ((uint64_t)d << 32) | j;
+                }
+            }
+            store_pair(r[0], r[1], nq, nt, split, out, qn);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Popcount matcher.  One query per lane; grid (query blocks of 256, splits).
 // key = (d << 21) | jl with d <= 512, jl < 2^21 - 1, so ~0u means "none".
 // ---------------------------------------------------------------------------
@@ -404,6 +610,20 @@ knn_mfma_kernel(SplitArgs a)
     const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
     mfma_item(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
               a.nsplit == 1 ? direct : part, tbuf);
+}
+
+__global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_fp4_kernel(SplitArgs a)
+{
+    __shared__ uint4 tbuf[2][kFp4TileVec];
+    __shared__ uint32_t lut_train[256], lut_query[256];
+    lut_train[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0x0u);
+    lut_query[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0xau);
+    __syncthreads();
+    const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
+    const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
+    fp4_item(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
+             a.nsplit == 1 ? direct : part, tbuf, lut_train, lut_query);
 }
 
 __global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
@@ -556,17 +776,18 @@ __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
 
 }  // namespace
 
-hipError_t launch_knn_split(const KnnSplitArgs &a, bool mfma, hipStream_t stream)
+hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_t stream)
 {
     const SplitArgs k{a.query, a.train, (int)a.plan.nq, (int)a.plan.nt, (int)a.plan.split_rows,
                       a.plan.nsplit, a.partial, a.k, a.ratio, a.idx, a.dist, a.accept};
     const int64_t qgroups = (a.plan.nq + 255) / 256;
-    if (mfma)
-        hipLaunchKernelGGL(knn_mfma_kernel, dim3((unsigned)qgroups, (unsigned)a.plan.nsplit),
-                           dim3(kMfmaThreads), 0, stream, k);
+    const dim3 grid((unsigned)qgroups, (unsigned)a.plan.nsplit);
+    if (which == SplitKernel::kMfmaI8)
+        hipLaunchKernelGGL(knn_mfma_kernel, grid, dim3(kMfmaThreads), 0, stream, k);
+    else if (which == SplitKernel::kMfmaFp4)
+        hipLaunchKernelGGL(knn_fp4_kernel, grid, dim3(kMfmaThreads), 0, stream, k);
     else
-        hipLaunchKernelGGL(knn_popcount_kernel, dim3((unsigned)qgroups, (unsigned)a.plan.nsplit),
-                           dim3(256), 0, stream, k);
+        hipLaunchKernelGGL(knn_popcount_kernel, grid, dim3(256), 0, stream, k);
     return hipGetLastError();
 }
 

@@ -171,13 +171,14 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
         return p;
     }
     const int64_t qgroups = (nq + 255) / 256;
-    const int64_t slots = (int64_t)num_cus *
-                          (path == LATCH_PATH_MFMA ? tune.mfma_groups_per_cu : tune.popcount_groups_per_cu);
+    const int64_t slots = (int64_t)num_cus * (path == LATCH_PATH_POPCOUNT ? tune.popcount_groups_per_cu
+                                                                        : tune.mfma_groups_per_cu);
     int64_t nsplit = qgroups >= slots ? 1 : slots / qgroups;
     const int64_t max_by_size = (tiles + 7) / 8;
     if (nsplit > max_by_size) nsplit = max_by_size;
     if (nsplit < 1) nsplit = 1;
-    const int64_t min_by_index = (nt + kMaxSplitRows - 1) / kMaxSplitRows;
+    const int64_t max_rows = path == LATCH_PATH_MFMA_FP4 ? kFp4MaxSplitRows : kMaxSplitRows;
+    const int64_t min_by_index = (nt + max_rows - 1) / max_rows;
     if (nsplit < min_by_index) nsplit = min_by_index;
     if (nsplit > 65535) nsplit = 65535;
     const int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
@@ -387,7 +388,7 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
     if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
     if (!(ratio > 0.0f && ratio <= 1.0f))
         return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
-    if (path != LATCH_PATH_AUTO && path != LATCH_PATH_MFMA && path != LATCH_PATH_POPCOUNT)
+    if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
         return fail(h, LATCH_EINVAL, "unknown path %d", path);
     if (nq == 0) return LATCH_OK;
     if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
@@ -410,10 +411,14 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
         if (rc != LATCH_OK) return rc;
         a.partial = reinterpret_cast<uint64_t *>(h->ws);
     }
-    const bool mfma = path == LATCH_PATH_MFMA;
-    hipError_t e = timed_launch(h, mfma ? "knn_mfma" : "knn_popcount", stream,
-                                [&] { return launch_knn_split(a, mfma, stream); });
-    if (e != hipSuccess) return hip_fail(h, e, mfma ? "mfma launch" : "popcount launch");
+    const SplitKernel which = path == LATCH_PATH_MFMA       ? SplitKernel::kMfmaI8
+                              : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
+                                                            : SplitKernel::kPopcount;
+    const char *name = which == SplitKernel::kMfmaI8    ? "knn_mfma"
+                       : which == SplitKernel::kMfmaFp4 ? "knn_fp4"
+                                                        : "knn_popcount";
+    hipError_t e = timed_launch(h, name, stream, [&] { return launch_knn_split(a, which, stream); });
+    if (e != hipSuccess) return hip_fail(h, e, name);
     if (a.plan.nsplit > 1) {
         e = timed_launch(h, "knn_merge", stream, [&] { return launch_knn_merge(a, stream); });
         if (e != hipSuccess) return hip_fail(h, e, "merge launch");
@@ -434,7 +439,8 @@ int latch_set_tuning(latch_handle h, const latch_tuning *t)
     auto ok_path = [](int p) { return p == LATCH_PATH_MFMA || p == LATCH_PATH_POPCOUNT; };
     for (int i = 0; i < 8; ++i)
         for (int j = 0; j < 8; ++j)
-            if (!ok_path(t->path[i][j])) return fail(h, LATCH_ERANGE, "tuning path[%d][%d]", i, j);
+            if (!ok_path(t->path[i][j]) && t->path[i][j] != LATCH_PATH_MFMA_FP4)
+                return fail(h, LATCH_ERANGE, "tuning path[%d][%d]", i, j);
     if (!ok_path(t->batch_path)) return fail(h, LATCH_ERANGE, "tuning batch_path");
     if (t->mfma_groups_per_cu < 1 || t->popcount_groups_per_cu < 1)
         return fail(h, LATCH_ERANGE, "tuning workgroup targets must be >= 1");
@@ -486,7 +492,7 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
     if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
     if (!(ratio > 0.0f && ratio <= 1.0f))
         return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
-    if (path != LATCH_PATH_AUTO && path != LATCH_PATH_MFMA && path != LATCH_PATH_POPCOUNT)
+    if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
         return fail(h, LATCH_EINVAL, "unknown path %d", path);
     if (n_pairs == 0) return LATCH_OK;
     if (!pairs_dev || !idx_dev || !dist_dev || (query_rows > 0 && !query_dev) ||
@@ -515,7 +521,7 @@ int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
     if (d->k != 1 && d->k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", d->k);
     if (!(d->ratio > 0.0f && d->ratio <= 1.0f))
         return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)d->ratio);
-    if (d->path != LATCH_PATH_AUTO && d->path != LATCH_PATH_MFMA && d->path != LATCH_PATH_POPCOUNT)
+    if (d->path < LATCH_PATH_AUTO || d->path > LATCH_PATH_MFMA_FP4)
         return fail(h, LATCH_EINVAL, "unknown path %d", d->path);
     if (!d->images || !d->image_id || !d->kps || !d->desc ||
         (d->n_pairs > 0 && (!d->pairs || !d->idx || !d->dist)))

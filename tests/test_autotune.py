@@ -54,9 +54,9 @@ def test_tuning_roundtrip_and_results_unchanged(triplets):
         for nq, nt in [(20, 5000), (3000, 3000), (700, 70)]:
             Q = synth.random_descriptors(g, nq)
             T = synth.random_descriptors(g, nt)
-            for path in ("mfma", "popcount"):             # force each path through the table
+            for code in (1, 2, 3):                         # force each path through the table
                 forced = dict(t)
-                forced["path"] = [[1 if path == "mfma" else 2] * 8 for _ in range(8)]
+                forced["path"] = [[code] * 8 for _ in range(8)]
                 lat.set_tuning(Tuning.from_dict(forced))
                 i, d, a = lat.knn(torch.from_numpy(Q.view(np.int32)).cuda(),
                                   torch.from_numpy(T.view(np.int32)).cuda(), path="auto")

@@ -1,4 +1,4 @@
-"""GPU parity: HIP 2-NN Hamming matching (MFMA and popcount paths) through the
+"""GPU parity: HIP 2-NN Hamming matching (int8 MFMA, MXFP4 MFMA and popcount paths) through the
 C ABI vs the CPU oracle, exact: indices, distances and ratio-test flags.
 
 Covers empty and tiny sets, sizes around the 32-row tile and 256-query group,
@@ -42,7 +42,7 @@ def gpu_knn(torch, lat, Q, T, k, ratio, path):
     return idx.cpu().numpy(), dist.cpu().numpy(), acc.cpu().numpy()
 
 
-def check(torch, lat, Q, T, k=2, ratio=0.8, paths=("mfma", "popcount")):
+def check(torch, lat, Q, T, k=2, ratio=0.8, paths=("mfma", "fp4", "popcount")):
     wi, wd, wa = oracle.knn(Q, T, k=k, ratio=ratio)
     for path in paths:
         gi, gd, ga = gpu_knn(torch, lat, Q, T, k, ratio, path)
@@ -159,3 +159,14 @@ def test_split_merge_repeated_calls(torch_cuda, lat):
         Q = synth.random_descriptors(g, nq)
         T = synth.random_descriptors(g, nt)
         check(torch_cuda, lat, Q, T, k=2)
+
+
+def test_fp4_split_boundaries(torch_cuda, lat):
+    """MXFP4 keys hold a 14-bit split-local index: train sets around and above
+    2^14 rows force several splits, with ties across split edges."""
+    g = np.random.default_rng(91)
+    for nq, nt in [(40, 16384), (40, 16385), (300, 16416), (97, 40000)]:
+        Q = synth.random_descriptors(g, nq, p_one=0.02)
+        T = synth.random_descriptors(g, nt, p_one=0.02)
+        T[-1] = T[0]                                  # an exact tie across the whole set
+        check(torch_cuda, lat, Q, T, paths=("fp4", "mfma"))
