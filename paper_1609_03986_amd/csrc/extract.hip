@@ -16,7 +16,10 @@
 //      row is one 8-byte-aligned quadword with a zero last byte;
 //   4. Eq. 1 (Sec. 3.1) for 512 triplets: each wavefront takes 4 rounds of 64
 //      lanes, one triplet per lane per round, in exact integer arithmetic;
-//   5. a 64-bit ballot per round packs the bits; 8 lanes per wavefront store
+//   5. a 64-bit ballot per round packs the bits.  Triplets sit in (round,
+//      lane) slots chosen on the host so that the 16-lane groups of a
+//      ds_read2_b64 hit few bank conflicts; four table lookups and ballots
+//      put the bits back in triplet order, and 8 lanes per wavefront store
 //      its 8 words.
 //
 // Patch distances.  With A, C the 7 x 7 patches of the anchor and one
@@ -61,6 +64,16 @@ static_assert(kCopyUnits > kThreads && kCopyUnits <= 2 * kThreads, "two copy uni
 static_assert(kWinLdsBytes * 8 <= kLdsPerCu, "eight windows per CU");
 
 typedef const __attribute__((address_space(1))) uint8_t GlobalByte;
+typedef __attribute__((address_space(1))) uint32_t GlobalWord;
+
+// A wavefront-uniform global pointer, kept in scalar registers.
+__device__ __forceinline__ GlobalWord *uniform_words(uint32_t *ptr)
+{
+    const uint64_t v = reinterpret_cast<uintptr_t>(ptr);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (GlobalWord *)(lo | (hi << 32));
+}
 
 // n / 2^22 rounded half away from zero, for |n| < 2^31 - 2^21.
 // n >= 0: floor((n + 2^21) / 2^22).  n < 0: floor((n + 2^21 - 1) / 2^22),
@@ -127,8 +140,7 @@ struct KeypointBatch {
     int cx, cy;
     int cs;          // C[b] & 0xffff | S[b] << 16
     int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18
-    int img_lo, img_hi;
-    int height, width, pitch;
+    int id;          // image table: the keypoint's image (0 when out of range)
 };
 
 template <bool kTable>
@@ -143,9 +155,11 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
     const uint8_t *img = src.img;
     int height = src.height, width = src.width, pitch = src.pitch;
     bool image_ok = true;
+    int image_id = 0;
     if (kTable) {
         const int id = real ? src.image_id[idx] : 0;
         image_ok = id >= 0 && id < src.n_images;
+        image_id = image_ok ? id : 0;
         const ImageEntry e = image_ok ? src.table[id] : ImageEntry{nullptr, 1, 1, 1, 0};
         img = e.img;
         height = e.height;
@@ -180,15 +194,13 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
     kb.cy = cy;
     kb.cs = (cs.x & 0xffff) | (cs.y << 16);
     kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18);
-    kb.img_lo = (int)(uint32_t)reinterpret_cast<uintptr_t>(img);
-    kb.img_hi = (int)(uint32_t)(reinterpret_cast<uintptr_t>(img) >> 32);
-    kb.height = height;
-    kb.width = width;
-    kb.pitch = pitch;
+    kb.id = image_id;
     return kb;
 }
 
-__device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bool *bad_image)
+template <bool kTable>
+__device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, const ImageSource &src,
+                                              bool *bad_image)
 {
     Keypoint k;
     k.cx = __builtin_amdgcn_readlane(kb.cx, j);
@@ -201,12 +213,20 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bo
     k.ok = (f >> 16) & 1;
     k.interior = (f >> 17) & 1;
     *bad_image = (f >> 18) & 1;
-    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane(kb.img_lo, j);
-    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane(kb.img_hi, j);
-    k.img = reinterpret_cast<const uint8_t *>(lo | (hi << 32));
-    k.height = __builtin_amdgcn_readlane(kb.height, j);
-    k.width = __builtin_amdgcn_readlane(kb.width, j);
-    k.pitch = __builtin_amdgcn_readlane(kb.pitch, j);
+    if (kTable) {
+        // The keypoint's image entry, a uniform (scalar) load; the entry was
+        // validated per lane in prepare_batch, and ok is false otherwise.
+        const ImageEntry e = src.table[__builtin_amdgcn_readlane(kb.id, j)];
+        k.img = e.img;
+        k.height = e.height;
+        k.width = e.width;
+        k.pitch = e.pitch;
+    } else {
+        k.img = src.img;
+        k.height = src.height;
+        k.width = src.width;
+        k.pitch = src.pitch;
+    }
     return k;
 }
 
@@ -217,7 +237,7 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, bo
 // members (the other two are 2 kRawCentre minus these).
 struct Slots {
     int uv[kSlots];
-    uint32_t raw[kSlots];
+    uint32_t raw[kSlots - 1];     // slot 5's is recomputed when written
 };
 
 __device__ __forceinline__ int pack_uv(int u, int v)
@@ -264,7 +284,8 @@ __device__ __forceinline__ Slots thread_slots(int tid)
         orbit_slot(kFullSlots * kThreads + tid, sl.uv[4], sl.raw[4]);
     else
         single_slot(tid - kSlot4Orbits, sl.uv[4], sl.raw[4]);
-    single_slot(kSlot4Singles + min(tid, kSlot5Singles - 1), sl.uv[5], sl.raw[5]);
+    uint32_t unused;
+    single_slot(kSlot4Singles + min(tid, kSlot5Singles - 1), sl.uv[5], unused);
     return sl;
 }
 
@@ -357,7 +378,11 @@ __device__ __forceinline__ void write_raw(uint8_t *lds, int tid, bool wave0, con
     for (int m = 0; m < kFullSlots; ++m)
         write_orbit(lds, sl.raw[m], true, g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
     write_orbit(lds, sl.raw[4], tid < kSlot4Orbits, g[16], g[17], g[18], g[19]);
-    if (wave0 && tid < kSlot5Singles) lds[sl.raw[5]] = (uint8_t)g[20];
+    if (wave0 && tid < kSlot5Singles) {
+        // Slot 5's address is recomputed here rather than held in a register.
+        const int uv = sl.uv[5];
+        lds[raw_addr((int)(short)(uv & 0xffff), uv >> 16)] = (uint8_t)g[20];
+    }
 }
 
 // Copy unit e = 5 y + q: from raw bytes (y, 8 q .. 8 q + 15) build the
@@ -433,8 +458,8 @@ __device__ __forceinline__ bool triplet_bit(const Rows &r)
 template <bool kTable>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void extract_kernel(
     ImageSource src, const float4 *__restrict__ kps, int64_t n_host, const int64_t *__restrict__ n_dev,
-    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off, uint32_t *__restrict__ desc,
-    uint32_t *__restrict__ flags)
+    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off,
+    const uint32_t *__restrict__ unperm, uint32_t *__restrict__ desc, uint32_t *__restrict__ flags)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kWinLdsBytes];
 
@@ -443,14 +468,23 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool wave0 = wave == 0;
 
-    // Wavefront w evaluates rounds 4 w .. 4 w + 3: triplet t = 64 r + lane in round r.
-    uint32_t off_a1[kRoundsPerWave], off_2[kRoundsPerWave];
+    // Wavefront w evaluates triplets 256 w .. 256 w + 255 in 4 rounds; slot
+    // 64 r + lane holds the triplet the bank-aware assignment put there, and
+    // `slots` names, for output bits 256 w + 64 k + lane, k = 0..3, the slots
+    // that computed them.
+    // Offsets: anchor | companion 1 << 16 per round, and the companion-2
+    // offsets of rounds 2 q and 2 q + 1 packed in off_2[q] (all < 2^16).
+    uint32_t off_a1[kRoundsPerWave], off_2[kRoundsPerWave / 2];
 #pragma unroll
     for (int r = 0; r < kRoundsPerWave; ++r) {
         const uint2 o = trip_off[64 * (kRoundsPerWave * wave + r) + lane];
         off_a1[r] = o.x;
-        off_2[r] = o.y;
+        if (r & 1)
+            off_2[r >> 1] |= o.y << 16;
+        else
+            off_2[r >> 1] = o.y;
     }
+    uint32_t *ballots = reinterpret_cast<uint32_t *>(lds + kBallotBase) + 8 * wave;
 
     // Keypoint count: a host value, or (batches) a device value capped by it.
     int64_t n = n_host;
@@ -462,13 +496,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     uint32_t g[kSamples];
     KeypointBatch batch = prepare_batch<kTable>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
-    Keypoint cur = batch_get(batch, 0, &bad_image);
+    Keypoint cur = batch_get<kTable>(batch, 0, src, &bad_image);
     if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
 
     for (int i = 0; p < n; ++i, p += stride) {
         const bool compute = cur.ok;
         if (!compute) {
-            if (tid < kWords) desc[p * kWords + tid] = 0u;
+            if (tid < kWords) uniform_words(desc + p * kWords)[(uint32_t)tid] = 0u;
             if (tid == 0) atomicOr(flags, bad_image ? kFlagBadImage : kFlagBadKeypoint);
         } else {
             // The raw window was last read by the previous descriptor's copy
@@ -483,22 +517,35 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         // Start the next keypoint's gather; it completes during the arithmetic below.
         const int j = (i + 1) & 63;
         if (j == 0) batch = prepare_batch<kTable>(kps, n, p + stride, stride, lane, rot, src);
-        cur = batch_get(batch, j, &bad_image);
+        cur = batch_get<kTable>(batch, j, src, &bad_image);
         if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
         if (!compute) continue;
 
-        // Eq. 1 for this wavefront's 256 triplets.
-        uint32_t out_word = 0;
+        // Eq. 1 for this wavefront's 256 triplets, in slot order.
+        uint32_t slot_word = 0;
 #pragma unroll
         for (int r = 0; r < kRoundsPerWave; ++r) {
             Rows rows;
-            load_rows(lds, off_a1[r] & 0xffffu, off_a1[r] >> 16, off_2[r], rows);
+            load_rows(lds, off_a1[r] & 0xffffu, off_a1[r] >> 16, (off_2[r >> 1] >> (16 * (r & 1))) & 0xffffu,
+                      rows);
             const uint64_t bits = __ballot(triplet_bit(rows));
-            if (lane == 2 * r) out_word = (uint32_t)bits;
-            if (lane == 2 * r + 1) out_word = (uint32_t)(bits >> 32);
+            if (lane == 2 * r) slot_word = (uint32_t)bits;
+            if (lane == 2 * r + 1) slot_word = (uint32_t)(bits >> 32);
+        }
+        // Back to triplet order through this wavefront's 8 ballot words in
+        // LDS (written and read by the same wavefront, so in order).
+        if (lane < 2 * kRoundsPerWave) ballots[lane] = slot_word;
+        const uint32_t slots = unperm[64 * wave + lane];
+        uint32_t out_word = 0;
+#pragma unroll
+        for (int k = 0; k < kRoundsPerWave; ++k) {
+            const uint32_t s = (slots >> (8 * k)) & 0xffu;
+            const uint64_t bits = __ballot((ballots[s >> 5] >> (s & 31u)) & 1u);
+            if (lane == 2 * k) out_word = (uint32_t)bits;
+            if (lane == 2 * k + 1) out_word = (uint32_t)(bits >> 32);
         }
         if (lane < 2 * kRoundsPerWave)
-            desc[p * kWords + 2 * kRoundsPerWave * wave + lane] = out_word;
+            uniform_words(desc + (p * kWords + 2 * kRoundsPerWave * wave))[(uint32_t)lane] = out_word;
     }
 }
 
@@ -513,10 +560,10 @@ hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream)
     ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
     if (a.table)
         hipLaunchKernelGGL(extract_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.desc, a.flags);
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.desc, a.flags);
     else
         hipLaunchKernelGGL(extract_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.desc, a.flags);
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.desc, a.flags);
     return hipGetLastError();
 }
 

@@ -34,7 +34,8 @@ constexpr int kEdgeBase = kCopies * kCopyBytes;                    // 15360
 constexpr int kEdgeBytes = kCopyBytes + 8;                         // 1928
 constexpr int kRawBase = (kEdgeBase + kEdgeBytes + 15) / 16 * 16;  // 17296
 constexpr int kRawStride = 52;
-constexpr int kWinLdsBytes = kRawBase + kWin * kRawStride;         // 19792 per workgroup
+constexpr int kBallotBase = kRawBase + kWin * kRawStride;          // 19792: 8 ballot words per wavefront
+constexpr int kWinLdsBytes = kBallotBase + 2 * 8 * 4;              // 19856 per workgroup
 constexpr int kExtractWaves = 2;                           // wavefronts per workgroup
 constexpr int kLdsPerCu = 160 * 1024;                      // gfx950
 
@@ -67,7 +68,8 @@ struct ExtractArgs {
     int64_t n;                     // keypoints (upper bound when n_dev is set)
     const int64_t *n_dev;          // optional device-side keypoint count
     const int2 *rot;          // [4096] {cos_q14, sin_q14}
-    const uint2 *trip_off;    // [512] {offA | off1 << 16, off2} LDS byte offsets
+    const uint2 *trip_off;    // [512] by slot: {offA | off1 << 16, off2} LDS byte offsets
+    const uint32_t *unperm;   // [128] per (wavefront, lane): slots of its four output bits
     uint32_t *desc;
     uint32_t *flags;
     int num_cus;

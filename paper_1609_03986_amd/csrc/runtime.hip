@@ -16,7 +16,8 @@ struct latch_ctx {
     int device = 0;
     int num_cus = 0;
     int2 *rot_dev = nullptr;           // [4096] {cos_q14, sin_q14}
-    uint2 *trip_off_dev = nullptr;     // [512] LDS byte offsets of the three patches
+    uint2 *trip_off_dev = nullptr;     // [512] by slot: LDS byte offsets of the three patches
+    uint32_t *unperm_dev = nullptr;    // [128] output-bit slots per (wavefront, lane)
     uint32_t *flags_dev = nullptr;     // sticky error word
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
@@ -82,6 +83,92 @@ uint32_t patch_offset(int r, int c)
     if (x < 8 * kCopyQwords)
         return (uint32_t)((x & 7) * kCopyBytes + y * kCopyRowBytes + 8 * (x >> 3));
     return (uint32_t)(kEdgeBase + 8 * (x - 8 * kCopyQwords) + y * kCopyRowBytes + 8 * (kCopyQwords - 1));
+}
+
+// Slot assignment of the extraction kernel.  Wavefront w evaluates triplets
+// 256 w .. 256 w + 255 in 4 rounds of 64 lanes; slot 64 r + l is lane l of
+// round r.  A ds_read2_b64 of a wavefront is served 16 lanes at a time, and
+// those 16 lanes read without bank conflicts when their quadword addresses
+// differ mod 16 (measured on gfx950; random addresses take about 2.5 times
+// as long).  Every patch row read of a lane is its patch offset plus a
+// uniform row offset, so the bank of all 7 rows follows from the patch
+// offset.  A deterministic annealing search over swaps puts triplets into
+// the 16 lane groups of a wavefront so that, per group and per patch (anchor,
+// companion 1, companion 2), the largest number of lanes sharing a bank is
+// as small as it gets.  slot_of[t] is the slot (within its wavefront) of
+// triplet t; results never depend on it, only speed does.
+void assign_slots(const uint2 *toff, uint8_t *slot_of)
+{
+    constexpr int kIters = 600000;
+    for (int w = 0; w < 2; ++w) {
+        int col[256][3];
+        for (int i = 0; i < 256; ++i) {
+            const uint2 o = toff[256 * w + i];
+            const uint32_t off[3] = {o.x & 0xffffu, o.x >> 16, o.y};
+            for (int k = 0; k < 3; ++k) col[i][k] = (int)((off[k] >> 3) & 15u);
+        }
+        int group_of[256], cnt[16][3][16];
+        std::memset(cnt, 0, sizeof cnt);
+        for (int i = 0; i < 256; ++i) {
+            group_of[i] = i / 16;
+            for (int k = 0; k < 3; ++k) ++cnt[group_of[i]][k][col[i][k]];
+        }
+        auto gmax = [&](int g, int k) {
+            int m = 0;
+            for (int c = 0; c < 16; ++c) m = cnt[g][k][c] > m ? cnt[g][k][c] : m;
+            return m;
+        };
+        uint32_t rs = 0x9e3779b9u + (uint32_t)w;
+        auto rnd = [&]() {
+            rs ^= rs << 13;
+            rs ^= rs >> 17;
+            rs ^= rs << 5;
+            return rs;
+        };
+        for (int it = 0; it < kIters; ++it) {
+            const int i = (int)(rnd() & 255u), j = (int)(rnd() & 255u);
+            const int G = group_of[i], H = group_of[j];
+            if (G == H) continue;
+            int before = 0, after = 0, sq = 0;
+            for (int k = 0; k < 3; ++k) before += gmax(G, k) + gmax(H, k);
+            for (int k = 0; k < 3; ++k) {
+                const int a = col[i][k], b = col[j][k];
+                if (a == b) continue;
+                sq += 2 * (cnt[G][k][b] - cnt[G][k][a] + 1) + 2 * (cnt[H][k][a] - cnt[H][k][b] + 1);
+                --cnt[G][k][a];
+                ++cnt[G][k][b];
+                --cnt[H][k][b];
+                ++cnt[H][k][a];
+            }
+            for (int k = 0; k < 3; ++k) after += gmax(G, k) + gmax(H, k);
+            // Objective: the summed largest bank multiplicity, then the sum of
+            // squared counts; worse moves pass with a probability that
+            // shrinks to zero over the search.
+            const int d = 64 * (after - before) + sq;
+            const double temp = 40.0 * (1.0 - (double)it / kIters);
+            const bool accept =
+                d <= 0 || (temp > 0.5 && (double)(rnd() & 0xffffu) < 65536.0 * std::exp(-d / temp));
+            if (accept) {
+                group_of[i] = H;
+                group_of[j] = G;
+            } else {
+                for (int k = 0; k < 3; ++k) {
+                    const int a = col[i][k], b = col[j][k];
+                    if (a == b) continue;
+                    ++cnt[G][k][a];
+                    --cnt[G][k][b];
+                    ++cnt[H][k][b];
+                    --cnt[H][k][a];
+                }
+            }
+        }
+        // Group g = 4 r + h is lanes 16 h .. 16 h + 15 of round r.
+        int fill[16] = {0};
+        for (int i = 0; i < 256; ++i) {
+            const int g = group_of[i];
+            slot_of[256 * w + i] = (uint8_t)(64 * (g >> 2) + 16 * (g & 3) + fill[g]++);
+        }
+    }
 }
 
 int ensure_workspace(latch_handle h, size_t need)
@@ -240,6 +327,7 @@ ExtractArgs batch_extract_args(latch_handle h, const latch_image *images_dev, in
     a.n_dev = n_kps_dev;
     a.rot = h->rot_dev;
     a.trip_off = h->trip_off_dev;
+    a.unperm = h->unperm_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
@@ -292,12 +380,26 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
         toff[t].x = patch_offset(tr[0], tr[1]) | (patch_offset(tr[2], tr[3]) << 16);
         toff[t].y = patch_offset(tr[4], tr[5]);
     }
+    // Triplets by slot, and per (wavefront w, lane l) the slots of output
+    // bits 256 w + 64 k + l, k = 0..3, one byte each.
+    uint8_t slot_of[kTriplets];
+    assign_slots(toff, slot_of);
+    uint2 toff_slot[kTriplets];
+    uint32_t unperm[2 * 64] = {};
+    for (int t = 0; t < kTriplets; ++t) {
+        const int w = t >> 8;
+        toff_slot[256 * w + slot_of[t]] = toff[t];
+        const int k = (t >> 6) & 3, l = t & 63;
+        unperm[64 * w + l] |= (uint32_t)slot_of[t] << (8 * k);
+    }
     int rc = LATCH_OK;
     if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->trip_off_dev, sizeof toff)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) != hipSuccess ||
         (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) != hipSuccess ||
         (e = hipMemcpy(h->rot_dev, rot, sizeof rot, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(h->trip_off_dev, toff, sizeof toff, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->trip_off_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->unperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemset(h->flags_dev, 0, sizeof(uint32_t))) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
@@ -314,6 +416,7 @@ void latch_destroy(latch_handle h)
     (void)hipDeviceSynchronize();
     if (h->rot_dev) (void)hipFree(h->rot_dev);
     if (h->trip_off_dev) (void)hipFree(h->trip_off_dev);
+    if (h->unperm_dev) (void)hipFree(h->unperm_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
     if (h->ws) (void)hipFree(h->ws);
     release_timed(h);
@@ -351,6 +454,7 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.n_dev = nullptr;
     a.rot = h->rot_dev;
     a.trip_off = h->trip_off_dev;
+    a.unperm = h->unperm_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
