@@ -268,8 +268,9 @@ int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
  * Tuning.  LATCH_PATH_AUTO picks the matcher path from a per-handle table
  * indexed by size buckets, bucket(n) = min(7, floor(log2(max(n, 1)) / 2)),
  * and the split planner of hamming_knn aims at the given number of
- * workgroups per CU.  Defaults: MFMA everywhere, 2 (MFMA) and 8 (popcount)
- * workgroups per CU.  Tuning never changes results, only speed.
+ * workgroups per CU.  Defaults: MFMA_FP4 everywhere (batches: MFMA), 2 (both
+ * MFMA paths) and 8 (popcount) workgroups per CU.  Tuning never changes
+ * results, only speed.
  */
 typedef struct {
     int8_t path[8][8];               /* [bucket(nq)][bucket(nt)]: LATCH_PATH_MFMA, _POPCOUNT or _MFMA_FP4 */

@@ -38,7 +38,7 @@ def choose(timings):
 def fill_table(measured):
     """measured: {(qb, tb): path}.  An 8 x 8 table whose unmeasured cells take
     the choice of the nearest measured cell (ties to the larger bucket)."""
-    table = [[MFMA] * 8 for _ in range(8)]
+    table = [[FP4] * 8 for _ in range(8)]
     if not measured:
         return table
     keys = list(measured)

@@ -240,7 +240,7 @@ int size_bucket(int64_t n)
 void default_tuning(latch_tuning *t)
 {
     std::memset(t, 0, sizeof *t);
-    std::memset(t->path, LATCH_PATH_MFMA, sizeof t->path);
+    std::memset(t->path, LATCH_PATH_MFMA_FP4, sizeof t->path);
     t->batch_path = LATCH_PATH_MFMA;
     t->mfma_groups_per_cu = 2;
     t->popcount_groups_per_cu = 8;

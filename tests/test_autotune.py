@@ -26,7 +26,7 @@ def test_choose_fastest_with_stable_ties():
 def test_fill_table_nearest_measured_bucket():
     t = autotune.fill_table({(2, 2): 2, (6, 6): 1})
     assert t[0][0] == 2 and t[2][3] == 2 and t[7][7] == 1 and t[5][6] == 1
-    assert autotune.fill_table({}) == [[1] * 8 for _ in range(8)]
+    assert autotune.fill_table({}) == [[3] * 8 for _ in range(8)]     # the library default, MXFP4
 
 
 @pytest.mark.gpu
