@@ -98,6 +98,7 @@ struct KnnSplitArgs {
 
 enum class SplitKernel { kMfmaI8, kMfmaFp4, kPopcount };
 constexpr int64_t kFp4MaxSplitRows = 1 << 14;    // MXFP4 keys hold a 14-bit split-local index
+constexpr int kFp4QueriesPerGroup = 256;         // queries per MXFP4 workgroup (64 per wavefront)
 
 hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_t stream);
 hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream);

@@ -191,13 +191,14 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     const int t_begin = split * tiles_per_split;
     const int t_end = min(ntiles_all, t_begin + tiles_per_split);
 
-    // Packed train tiles in flight: ld0 is staged next, ld1 and ld2 follow.
-    // A tile's MFMAs take about 1000 cycles, less than an L2 miss, so loads
-    // are issued three tiles ahead of their use.
-    uint2 ld0 = make_uint2(0, 0), ld1 = ld0, ld2 = ld0;
+    // Packed train tiles in flight.  A tile's MFMAs take about 1000 cycles,
+    // less than an L2 miss, so a tile's load is issued two tiles before it is
+    // staged; the loop is unrolled by two so that the two prefetch registers
+    // are never copied (a copy would wait for the load).
+    uint2 ld0 = make_uint2(0, 0), ra = ld0, rb = ld0;
     if (t_begin < t_end) ld0 = load_tile(train, nt, t_begin, tid);
-    if (t_begin + 1 < t_end) ld1 = load_tile(train, nt, t_begin + 1, tid);
-    if (t_begin + 2 < t_end) ld2 = load_tile(train, nt, t_begin + 2, tid);
+    if (t_begin + 1 < t_end) ra = load_tile(train, nt, t_begin + 1, tid);
+    if (t_begin + 2 < t_end) rb = load_tile(train, nt, t_begin + 2, tid);
 
     // Resident query fragments and query popcounts.
     v4i bq[kQueryBlocks][16];
@@ -223,12 +224,8 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     if (t_begin < t_end) stage_tile(ld0, tid, tbuf[0]);
     __syncthreads();
 
-    for (int tile = t_begin; tile < t_end; ++tile) {
-        const int buf = (tile - t_begin) & 1;
-        const bool more = tile + 1 < t_end;
-        uint2 ld3 = make_uint2(0, 0);
-        if (tile + 3 < t_end) ld3 = load_tile(train, nt, tile + 3, tid);
-
+    // One tile: MFMAs over LDS buffer `buf`, then the top-2 update.
+    auto tile_step = [&](int tile, int buf) {
         v16i acc[kQueryBlocks];
 #pragma unroll
         for (int qb = 0; qb < kQueryBlocks; ++qb) acc[qb] = (v16i){};
@@ -267,10 +264,21 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
                 k1[qb] = max(k1[qb], key);
             }
         }
+    };
 
-        if (more) stage_tile(ld1, tid, tbuf[buf ^ 1]);
-        ld1 = ld2;
-        ld2 = ld3;
+    // Straight-line body (a branch around a load or a stage makes the
+    // compiler wait for every outstanding load): loads past the split read
+    // train rows of the next split or none (rows past nt load nothing and
+    // give zeros), and staging into the idle buffer is harmless.
+    for (int tile = t_begin; tile < t_end; tile += 2) {
+        tile_step(tile, 0);
+        stage_tile(ra, tid, tbuf[1]);
+        ra = load_tile(train, nt, tile + 3, tid);
+        __syncthreads();
+        if (tile + 1 >= t_end) break;
+        tile_step(tile + 1, 1);
+        stage_tile(rb, tid, tbuf[0]);
+        rb = load_tile(train, nt, tile + 4, tid);
         __syncthreads();
     }
 
@@ -336,6 +344,9 @@ constexpr int kFp4TileVec = kFp4Steps * 64;           // 16-byte fragments per t
 constexpr int kFp4ScaleTrain = 127;                   // E8M0 2^0
 constexpr int kFp4ScaleQuery = 127 + 14;              // E8M0 2^14
 constexpr float kFp4None = -33554432.0f;              // -2^25
+// Query blocks of 32 per wavefront: each train fragment read from LDS feeds
+// this many MFMAs.
+constexpr int kFp4QueryBlocks = kFp4QueriesPerGroup / (kMfmaWaves * 32);
 
 // Byte -> 8 FP4 nibbles (bit e -> nibble e): `one` for a set bit, `zero` for a clear one.
 __device__ __forceinline__ uint32_t fp4_byte(uint32_t byte, uint32_t one, uint32_t zero)
@@ -381,6 +392,7 @@ __device__ __forceinline__ void stage_tile_fp4(uint2 w, int tid, const uint32_t 
     buf[s * 64 + 32 + r] = fp4_word(w.y, lut);
 }
 
+template <int QB>
 __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int nq,
                                          const uint32_t *__restrict__ train, int nt, int qgroup,
                                          int split, int split_rows, const ItemOut &out,
@@ -391,23 +403,24 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     const int lane = tid & 63;
     const int half = lane >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int qbase = qgroup * kQueriesPerGroup + wave * kQueriesPerWave;
+    const int qbase = qgroup * (kMfmaWaves * 32 * QB) + wave * (32 * QB);
 
     const int ntiles_all = (nt + kTileRows - 1) / kTileRows;
     const int tiles_per_split = split_rows / kTileRows;
     const int t_begin = split * tiles_per_split;
     const int t_end = min(ntiles_all, t_begin + tiles_per_split);
 
-    uint2 ld0 = make_uint2(0, 0), ld1 = ld0, ld2 = ld0;
+    // Tile loads two tiles ahead of staging, as in the int8 path.
+    uint2 ld0 = make_uint2(0, 0), ra = ld0, rb = ld0;
     if (t_begin < t_end) ld0 = load_tile(train, nt, t_begin, tid);
-    if (t_begin + 1 < t_end) ld1 = load_tile(train, nt, t_begin + 1, tid);
-    if (t_begin + 2 < t_end) ld2 = load_tile(train, nt, t_begin + 2, tid);
+    if (t_begin + 1 < t_end) ra = load_tile(train, nt, t_begin + 1, tid);
+    if (t_begin + 2 < t_end) rb = load_tile(train, nt, t_begin + 2, tid);
 
     // Resident query fragments (+-1) and query popcounts.
-    uint4 bq[kQueryBlocks][kFp4Steps];
-    int na[kQueryBlocks];
+    uint4 bq[QB][kFp4Steps];
+    int na[QB];
 #pragma unroll
-    for (int qb = 0; qb < kQueryBlocks; ++qb) {
+    for (int qb = 0; qb < QB; ++qb) {
         const int qn = qbase + 32 * qb + (lane & 31);
         int pc = 0;
 #pragma unroll
@@ -420,9 +433,9 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
         na[qb] = pc;
     }
 
-    float k1[kQueryBlocks], k2[kQueryBlocks];
+    float k1[QB], k2[QB];
 #pragma unroll
-    for (int qb = 0; qb < kQueryBlocks; ++qb) k1[qb] = k2[qb] = kFp4None;
+    for (int qb = 0; qb < QB; ++qb) k1[qb] = k2[qb] = kFp4None;
 
     // Accumulator start values c_m; register r = 4 g + e holds tile row
     // m = 8 g + 4 half + e.
@@ -433,18 +446,14 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     if (t_begin < t_end) stage_tile_fp4(ld0, tid, lut_train, tbuf[0]);
     __syncthreads();
 
-    for (int tile = t_begin; tile < t_end; ++tile) {
-        const int buf = (tile - t_begin) & 1;
-        const bool more = tile + 1 < t_end;
-        uint2 ld3 = make_uint2(0, 0);
-        if (tile + 3 < t_end) ld3 = load_tile(train, nt, tile + 3, tid);
-
-        v16f acc[kQueryBlocks];
+    // One tile: MFMAs over LDS buffer `buf`, then the top-2 update.
+    auto tile_step = [&](int tile, int buf) {
+        v16f acc[QB];
 #pragma unroll
         for (int s = 0; s < kFp4Steps; ++s) {
             const v8i a = fp4_operand(tbuf[buf][s * 64 + lane]);
 #pragma unroll
-            for (int qb = 0; qb < kQueryBlocks; ++qb)
+            for (int qb = 0; qb < QB; ++qb)
                 acc[qb] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
                     a, fp4_operand(bq[qb][s]), s == 0 ? c0 : acc[qb], 4, 4, 0, kFp4ScaleTrain, 0,
                     kFp4ScaleQuery);
@@ -455,11 +464,11 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
             for (int r = 0; r < 16; ++r)
                 if (8 * (r >> 2) + 4 * half + (r & 3) >= valid_rows)
 #pragma unroll
-                    for (int qb = 0; qb < kQueryBlocks; ++qb) acc[qb][r] = kFp4None;
+                    for (int qb = 0; qb < QB; ++qb) acc[qb][r] = kFp4None;
         }
         // Move the running top-2 into this tile's frame, then update it.
 #pragma unroll
-        for (int qb = 0; qb < kQueryBlocks; ++qb) {
+        for (int qb = 0; qb < QB; ++qb) {
             if (tile != t_begin) {
                 k1[qb] += 32.0f;
                 k2[qb] += 32.0f;
@@ -472,9 +481,18 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
             }
         }
 
-        if (more) stage_tile_fp4(ld1, tid, lut_train, tbuf[buf ^ 1]);
-        ld1 = ld2;
-        ld2 = ld3;
+    };
+
+    // Straight-line body, as in the int8 path.
+    for (int tile = t_begin; tile < t_end; tile += 2) {
+        tile_step(tile, 0);
+        stage_tile_fp4(ra, tid, lut_train, tbuf[1]);
+        ra = load_tile(train, nt, tile + 3, tid);
+        __syncthreads();
+        if (tile + 1 >= t_end) break;
+        tile_step(tile + 1, 1);
+        stage_tile_fp4(rb, tid, lut_train, tbuf[0]);
+        rb = load_tile(train, nt, tile + 4, tid);
         __syncthreads();
     }
 
@@ -482,7 +500,7 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     // key = 2^14 (|a| - d) + 2^14 - 1 - jl + 32 (tiles - 1).
     const int shift = 32 * max(t_end - t_begin - 1, 0);
 #pragma unroll
-    for (int qb = 0; qb < kQueryBlocks; ++qb) {
+    for (int qb = 0; qb < QB; ++qb) {
         const float o1 = __shfl_xor(k1[qb], 32);
         const float o2 = __shfl_xor(k2[qb], 32);
         const float b1 = fmaxf(k1[qb], o1);
@@ -622,8 +640,8 @@ knn_fp4_kernel(SplitArgs a)
     __syncthreads();
     const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
     const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
-    fp4_item(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
-             a.nsplit == 1 ? direct : part, tbuf, lut_train, lut_query);
+    fp4_item<kFp4QueryBlocks>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
+                              a.nsplit == 1 ? direct : part, tbuf, lut_train, lut_query);
 }
 
 __global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
@@ -780,7 +798,8 @@ hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_
 {
     const SplitArgs k{a.query, a.train, (int)a.plan.nq, (int)a.plan.nt, (int)a.plan.split_rows,
                       a.plan.nsplit, a.partial, a.k, a.ratio, a.idx, a.dist, a.accept};
-    const int64_t qgroups = (a.plan.nq + 255) / 256;
+    const int64_t group = which == SplitKernel::kMfmaFp4 ? kFp4QueriesPerGroup : 256;
+    const int64_t qgroups = (a.plan.nq + group - 1) / group;
     const dim3 grid((unsigned)qgroups, (unsigned)a.plan.nsplit);
     if (which == SplitKernel::kMfmaI8)
         hipLaunchKernelGGL(knn_mfma_kernel, grid, dim3(kMfmaThreads), 0, stream, k);

@@ -257,7 +257,8 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
         p.split_rows = kTileRows;
         return p;
     }
-    const int64_t qgroups = (nq + 255) / 256;
+    const int64_t group = path == LATCH_PATH_MFMA_FP4 ? kFp4QueriesPerGroup : 256;
+    const int64_t qgroups = (nq + group - 1) / group;
     const int64_t slots = (int64_t)num_cus * (path == LATCH_PATH_POPCOUNT ? tune.popcount_groups_per_cu
                                                                         : tune.mfma_groups_per_cu);
     int64_t nsplit = qgroups >= slots ? 1 : slots / qgroups;

@@ -117,3 +117,24 @@ def test_large_uneven_batch_sampled(torch_cuda, lat, triplets):
     want, f = oracle_batch(imgs, kps[sel], ids[sel], triplets)
     assert f == 0 and lat.check_errors(clear=True) == 0
     assert np.array_equal(got[sel], want)
+
+
+def test_bench_step_configuration(torch_cuda, lat, triplets):
+    """The launch bench.py times: both 1920x1080 images of the 10,000-keypoint
+    workload in one batched launch; every descriptor bit-exact."""
+    torch = torch_cuda
+    from paper_1609_03986_amd.binding import image_table
+    w = synth.workload_hd()
+    nq, nt = len(w["query_kps"]), len(w["train_kps"])
+    imgs = [torch.from_numpy(w["query_image"]).cuda(), torch.from_numpy(w["train_image"]).cuda()]
+    kps = torch.from_numpy(np.concatenate([w["query_kps"], w["train_kps"]])).cuda()
+    ids = torch.from_numpy(np.repeat(np.arange(2, dtype=np.int32), [nq, nt])).cuda()
+    desc = lat.extract_batch(image_table(imgs), 2, ids, kps)
+    torch.cuda.synchronize()
+    got = desc.cpu().numpy().view(np.uint32)
+    oq, f1 = oracle.extract(w["query_image"], w["query_kps"], triplets)
+    ot, f2 = oracle.extract(w["train_image"], w["train_kps"], triplets)
+    assert f1 == 0 and f2 == 0
+    assert np.array_equal(got[:nq], oq)
+    assert np.array_equal(got[nq:], ot)
+    assert lat.check_errors() == 0
