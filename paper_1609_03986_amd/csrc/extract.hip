@@ -250,9 +250,24 @@ __device__ __forceinline__ uint32_t raw_addr(int u, int v)
     return (uint32_t)(kRawCentre + v * kRawStride + u);
 }
 
+// Orbit o -> representative (u, v), u in [1, 23], v in [0, 23], in 8 x 8
+// blocks (u 1..8, 9..16, 17..23 within each band of 8 v), so that the 64
+// lanes of one load instruction sample a compact patch of the image and
+// touch few cache lines whatever the rotation.
 __device__ __forceinline__ void orbit_slot(int o, int &uv, uint32_t &raw)
 {
-    const int v = o / kOrbitU, u = o - kOrbitU * v + 1;
+    constexpr int kBand = kOrbitU * 8;                    // 184 orbits per band of 8 rows
+    const int vb = o / kBand, r = o - kBand * vb;
+    int u, v;
+    if (r < 128) {
+        const int ub = r >> 6, i = r & 63;
+        u = 8 * ub + (i & 7) + 1;
+        v = 8 * vb + (i >> 3);
+    } else {
+        const int i = r - 128;                            // the 7-wide block, u 17..23
+        u = 17 + i % 7;
+        v = 8 * vb + i / 7;
+    }
     uv = pack_uv(u, v);
     raw = raw_addr(u, v) | (raw_addr(-v, u) << 16);
 }
