@@ -572,29 +572,6 @@ __device__ __forceinline__ void popcount_item(const uint32_t *__restrict__ query
 // integer order is the lexicographic one) and apply the ratio test exactly:
 // a float32 ratio times an integer <= 512 is exact in double.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void merge_query(const uint64_t *__restrict__ partial, int nq, int nsplit,
-                                            int nt, const ItemOut &out, int q)
-{
-    uint64_t b1 = kNoNeighbour, b2 = kNoNeighbour;
-    // Eight splits' loads in flight at a time, then a branch-free top-2 update.
-    for (int s0 = 0; s0 < nsplit; s0 += 8) {
-        uint64_t v[16];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const bool in = s0 + i < nsplit;
-            const uint64_t *src = partial + ((size_t)(in ? s0 + i : 0) * nq + q) * 2;
-            v[2 * i] = in ? src[0] : kNoNeighbour;
-            v[2 * i + 1] = in ? src[1] : kNoNeighbour;
-        }
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            b2 = min(b2, max(b1, v[i]));
-            b1 = min(b1, v[i]);
-        }
-    }
-    store_final(b1, b2, nt, out, q);
-}
-
 // Arguments of the split matchers.  nsplit == 1: results go straight to
 // idx / dist / accept; otherwise per-(split, query) partials for the merge
 // kernel.
@@ -609,15 +586,49 @@ struct SplitArgs {
     uint8_t *accept;
 };
 
+// The two smallest of the pairs (a1 <= a2) and (c1 <= c2).
+__device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c1, uint64_t c2)
+{
+    const uint64_t lo = min(a1, c1);
+    a2 = min(max(a1, c1), min(a2, c2));
+    a1 = lo;
+}
+
+__device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
+{
+    const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Four lanes per query: lane g of a query reads splits g, g + 4, ... (all
+// loads in flight), then two shuffle rounds combine the four top-2 pairs.
+constexpr int kMergeLanes = 4;
+
 __global__ __launch_bounds__(256) void knn_merge_kernel(const uint64_t *__restrict__ partial, int nq,
                                                         int nsplit, int nt, int k, float ratio,
                                                         int32_t *__restrict__ idx,
                                                         int32_t *__restrict__ dist,
                                                         uint8_t *__restrict__ accept)
 {
-    const int q = blockIdx.x * 256 + threadIdx.x;
-    if (q >= nq) return;
-    merge_query(partial, nq, nsplit, nt, ItemOut{nullptr, idx, dist, accept, k, ratio}, q);
+    const int g = threadIdx.x & (kMergeLanes - 1);
+    const int q = blockIdx.x * (256 / kMergeLanes) + threadIdx.x / kMergeLanes;
+    const bool real = q < nq;
+    uint64_t b1 = kNoNeighbour, b2 = kNoNeighbour;
+    for (int s0 = g; s0 < nsplit; s0 += 4 * kMergeLanes) {
+        ulonglong2 v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int sp = s0 + kMergeLanes * i;
+            v[i] = real && sp < nsplit
+                       ? reinterpret_cast<const ulonglong2 *>(partial)[(size_t)sp * nq + q]
+                       : make_ulonglong2(kNoNeighbour, kNoNeighbour);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) top2_pair(b1, b2, v[i].x, v[i].y);
+    }
+#pragma unroll
+    for (int m = 1; m < kMergeLanes; m <<= 1) top2_pair(b1, b2, shfl_xor_u64(b1, m), shfl_xor_u64(b2, m));
+    if (real && g == 0) store_final(b1, b2, nt, ItemOut{nullptr, idx, dist, accept, k, ratio}, q);
 }
 
 __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
@@ -812,7 +823,8 @@ hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_
 
 hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream)
 {
-    const int64_t blocks = (a.plan.nq + 255) / 256;
+    const int64_t per_block = 256 / kMergeLanes;
+    const int64_t blocks = (a.plan.nq + per_block - 1) / per_block;
     hipLaunchKernelGGL(knn_merge_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, a.partial,
                        (int)a.plan.nq, a.plan.nsplit, (int)a.plan.nt, a.k, a.ratio, a.idx, a.dist,
                        a.accept);
