@@ -80,8 +80,7 @@ typedef enum {
     LATCH_PATH_MFMA = 1,      /* int8 MFMA: sum of (2a - 1) b over 0/1 bits = |a| - Hamming */
     LATCH_PATH_POPCOUNT = 2,  /* XOR + popcount */
     LATCH_PATH_MFMA_FP4 = 3   /* block-scaled FP4 MFMA (values 0, +-1 are exact in e2m1; sums
-                                 accumulate exactly in f32): twice the int8 MFMA rate.  Batched
-                                 matching runs it as LATCH_PATH_MFMA. */
+                                 accumulate exactly in f32): twice the int8 MFMA rate */
 } latch_path;
 
 /* Bits of the sticky device error word. */
@@ -268,20 +267,20 @@ int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
  * Tuning.  LATCH_PATH_AUTO picks the matcher path from a per-handle table
  * indexed by size buckets, bucket(n) = min(7, floor(log2(max(n, 1)) / 2)),
  * and the split planner of hamming_knn aims at the given number of
- * workgroups per CU.  Defaults: MFMA_FP4 everywhere (batches: MFMA), 2 (both
+ * workgroups per CU.  Defaults: MFMA_FP4 everywhere (batches too), 2 (both
  * MFMA paths) and 8 (popcount) workgroups per CU.  Tuning never changes
  * results, only speed.
  */
 typedef struct {
     int8_t path[8][8];               /* [bucket(nq)][bucket(nt)]: LATCH_PATH_MFMA, _POPCOUNT or _MFMA_FP4 */
-    int8_t batch_path;               /* path of batched matching under LATCH_PATH_AUTO: MFMA or POPCOUNT */
+    int8_t batch_path;               /* path of batched matching under LATCH_PATH_AUTO */
     int8_t reserved[3];
     int32_t mfma_groups_per_cu;      /* >= 1 */
     int32_t popcount_groups_per_cu;  /* >= 1 */
 } latch_tuning;
 
 int latch_get_tuning(latch_handle h, latch_tuning *out);
-/* LATCH_ERANGE if a path entry is not a valid path (batch_path: MFMA or POPCOUNT) or a target is < 1. */
+/* LATCH_ERANGE if a path entry is not MFMA, POPCOUNT or MFMA_FP4, or a target is < 1. */
 int latch_set_tuning(latch_handle h, const latch_tuning *t);
 
 /*
@@ -290,7 +289,7 @@ int latch_set_tuning(latch_handle h, const latch_tuning *t);
  * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops
  * recording).  latch_timing_read waits for the recorded events and returns,
  * for one kernel name ("extract", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge",
- * "knn_batch_mfma", "knn_batch_popcount"; the batch names cover the whole
+ * "knn_batch_mfma", "knn_batch_fp4", "knn_batch_popcount"; the batch names cover the whole
  * batched sequence), the number of launches recorded and their summed
  * duration in milliseconds.  Not for use under stream capture.
  */

@@ -1,7 +1,6 @@
 """Autotuner for the matcher: picks, per (query count, train count) size
 bucket, the fastest of the int8-MFMA, MXFP4-MFMA and popcount paths, the
-path for batched matching (int8 MFMA or popcount), and the split planner's
-workgroups-per-CU target.  It
+path for batched matching, and the split planner's workgroups-per-CU target.  It
 measures the library's own kernels (HIP events recorded by the library on
 its launch stream) on random descriptors and caches the result per device
 and library version.
@@ -103,7 +102,7 @@ def tune(lat, buckets=None, reps=5, seed=0, log=None):
     if log:
         log("mfma workgroups per CU: %s -> %d" %
             ({w: round(v * 1e6, 1) for w, v in targets.items()}, tuning["mfma_groups_per_cu"]))
-    tuning["batch_path"] = POPCOUNT if tuning["path"][6][6] == POPCOUNT else MFMA
+    tuning["batch_path"] = tuning["path"][6][6]
     lat.set_tuning(Tuning.from_dict(tuning))
     return tuning
 

@@ -86,6 +86,9 @@ struct KnnPlan {
 // Single-pair matching over train splits.  With one split the results are
 // written directly; otherwise each (split, query) writes its two best as
 // partials and launch_knn_merge reduces them.
+// Which matcher kernel runs.
+enum class SplitKernel { kMfmaI8, kMfmaFp4, kPopcount };
+
 struct KnnSplitArgs {
     const uint32_t *query, *train;
     KnnPlan plan;
@@ -96,7 +99,6 @@ struct KnnSplitArgs {
     uint8_t *accept;
 };
 
-enum class SplitKernel { kMfmaI8, kMfmaFp4, kPopcount };
 constexpr int64_t kFp4MaxSplitRows = 1 << 14;    // MXFP4 keys hold a 14-bit split-local index
 constexpr int kFp4QueriesPerGroup = 256;         // queries per MXFP4 workgroup (64 per wavefront)
 
@@ -121,6 +123,7 @@ struct BatchState {          // batch header in the workspace
     uint32_t pad;
 };
 
+
 struct BatchArgs {
     const uint32_t *query, *train;
     int64_t query_rows, train_rows, out_rows;
@@ -136,7 +139,7 @@ struct BatchArgs {
     uint8_t *accept;
     uint32_t *flags;
     int num_cus;
-    bool mfma;
+    SplitKernel kind;
 };
 
 hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream);

@@ -191,14 +191,10 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     const int t_begin = split * tiles_per_split;
     const int t_end = min(ntiles_all, t_begin + tiles_per_split);
 
-    // Packed train tiles in flight.  A tile's MFMAs take about 1000 cycles,
-    // less than an L2 miss, so a tile's load is issued two tiles before it is
-    // staged; the loop is unrolled by two so that the two prefetch registers
-    // are never copied (a copy would wait for the load).
-    uint2 ld0 = make_uint2(0, 0), ra = ld0, rb = ld0;
+    // The next tile's load is issued at the start of a tile and staged at
+    // its end (the query fragments leave no registers for a deeper queue).
+    uint2 ld0 = make_uint2(0, 0);
     if (t_begin < t_end) ld0 = load_tile(train, nt, t_begin, tid);
-    if (t_begin + 1 < t_end) ra = load_tile(train, nt, t_begin + 1, tid);
-    if (t_begin + 2 < t_end) rb = load_tile(train, nt, t_begin + 2, tid);
 
     // Resident query fragments and query popcounts.
     v4i bq[kQueryBlocks][16];
@@ -266,19 +262,14 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
         }
     };
 
-    // Straight-line body (a branch around a load or a stage makes the
-    // compiler wait for every outstanding load): loads past the split read
-    // train rows of the next split or none (rows past nt load nothing and
-    // give zeros), and staging into the idle buffer is harmless.
-    for (int tile = t_begin; tile < t_end; tile += 2) {
-        tile_step(tile, 0);
-        stage_tile(ra, tid, tbuf[1]);
-        ra = load_tile(train, nt, tile + 3, tid);
-        __syncthreads();
-        if (tile + 1 >= t_end) break;
-        tile_step(tile + 1, 1);
-        stage_tile(rb, tid, tbuf[0]);
-        rb = load_tile(train, nt, tile + 4, tid);
+    // Straight-line body: the load past the split reads train rows of the
+    // next split or none (rows past nt load nothing and give zeros), and
+    // staging into the idle buffer is harmless.
+    for (int tile = t_begin; tile < t_end; ++tile) {
+        const int buf = (tile - t_begin) & 1;
+        const uint2 ld = load_tile(train, nt, tile + 1, tid);
+        tile_step(tile, buf);
+        stage_tile(ld, tid, tbuf[buf ^ 1]);
         __syncthreads();
     }
 
@@ -308,6 +299,14 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
             store_pair(r[0], r[1], nq, nt, split, out, qn);
         }
     }
+}
+
+// The two smallest of the pairs (a1 <= a2) and (c1 <= c2).
+__device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c1, uint64_t c2)
+{
+    const uint64_t lo = min(a1, c1);
+    a2 = min(max(a1, c1), min(a2, c2));
+    a1 = lo;
 }
 
 // ---------------------------------------------------------------------------
@@ -392,10 +391,13 @@ __device__ __forceinline__ void stage_tile_fp4(uint2 w, int tid, const uint32_t 
     buf[s * 64 + 32 + r] = fp4_word(w.y, lut);
 }
 
+// One (query group, train range) of the MXFP4 matcher.  Train rows
+// split * split_rows .. + split_rows - 1 (split_rows <= 2^14); each lane's
+// queries' best two (distance << 32 | index) are merged into best[qb].
 template <int QB>
 __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int nq,
                                          const uint32_t *__restrict__ train, int nt, int qgroup,
-                                         int split, int split_rows, const ItemOut &out,
+                                         int split, int split_rows, uint64_t (&best)[QB][2],
                                          uint4 (*tbuf)[kFp4TileVec], const uint32_t *lut_train,
                                          const uint32_t *lut_query)
 {
@@ -443,6 +445,7 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
 #pragma unroll
     for (int r = 0; r < 16; ++r) c0[r] = (float)((1 << 14) - 1 - (8 * (r >> 2) + 4 * half + (r & 3)));
 
+    __syncthreads();       // the staging buffers may still be read for a previous range
     if (t_begin < t_end) stage_tile_fp4(ld0, tid, lut_train, tbuf[0]);
     __syncthreads();
 
@@ -505,24 +508,42 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
         const float o2 = __shfl_xor(k2[qb], 32);
         const float b1 = fmaxf(k1[qb], o1);
         const float b2 = fmaxf(fminf(k1[qb], o1), fmaxf(k2[qb], o2));
-        const int qn = qbase + 32 * qb + (lane & 31);
-        if (half == 0 && qn < nq) {
-            uint64_t r[2];
-            const float kk[2] = {b1, b2};
+        uint64_t r[2];
+        const float kk[2] = {b1, b2};
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
-                if (kk[e] < -16777216.0f) {                  // a row past nt, or none
-                    r[e] = kNoNeighbour;
-                } else {
-                    const int key = (int)kk[e] - shift;
-                    const uint32_t d = (uint32_t)(na[qb] - (key >> 14));
-                    const uint32_t j = (uint32_t)split * (uint32_t)split_rows +
-                                       (uint32_t)((1 << 14) - 1 - (key & 0x3fff));
-                    r[e] = ((uint64_t)d << 32) | j;
-                }
+        for (int e = 0; e < 2; ++e) {
+            if (kk[e] < -16777216.0f) {                  // a row past nt, or none
+                r[e] = kNoNeighbour;
+            } else {
+                const int key = (int)kk[e] - shift;
+                const uint32_t d = (uint32_t)(na[qb] - (key >> 14));
+                const uint32_t j = (uint32_t)split * (uint32_t)split_rows +
+                                   (uint32_t)((1 << 14) - 1 - (key & 0x3fff));
+                r[e] = ((uint64_t)d << 32) | j;
             }
-            store_pair(r[0], r[1], nq, nt, split, out, qn);
         }
+        top2_pair(best[qb][0], best[qb][1], r[0], r[1]);
+    }
+}
+
+template <int QB>
+__device__ __forceinline__ void fp4_init_best(uint64_t (&best)[QB][2])
+{
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) best[qb][0] = best[qb][1] = kNoNeighbour;
+}
+
+// Lanes 0..31 of each wavefront store their queries' results.
+template <int QB>
+__device__ __forceinline__ void fp4_store(const uint64_t (&best)[QB][2], int nq, int nt, int qgroup,
+                                          int split, const ItemOut &out)
+{
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) {
+        const int qn = qgroup * (kMfmaWaves * 32 * QB) + wave * (32 * QB) + 32 * qb + (lane & 31);
+        if (lane < 32 && qn < nq) store_pair(best[qb][0], best[qb][1], nq, nt, split, out, qn);
     }
 }
 
@@ -586,14 +607,6 @@ struct SplitArgs {
     uint8_t *accept;
 };
 
-// The two smallest of the pairs (a1 <= a2) and (c1 <= c2).
-__device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c1, uint64_t c2)
-{
-    const uint64_t lo = min(a1, c1);
-    a2 = min(max(a1, c1), min(a2, c2));
-    a1 = lo;
-}
-
 __device__ __forceinline__ uint64_t shfl_xor_u64(uint64_t v, int m)
 {
     const uint32_t lo = __shfl_xor((uint32_t)v, m), hi = __shfl_xor((uint32_t)(v >> 32), m);
@@ -651,8 +664,11 @@ knn_fp4_kernel(SplitArgs a)
     __syncthreads();
     const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
     const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
+    uint64_t best[kFp4QueryBlocks][2];
+    fp4_init_best(best);
     fp4_item<kFp4QueryBlocks>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
-                              a.nsplit == 1 ? direct : part, tbuf, lut_train, lut_query);
+                              best, tbuf, lut_train, lut_query);
+    fp4_store(best, a.nq, a.nt, blockIdx.x, blockIdx.y, a.nsplit == 1 ? direct : part);
 }
 
 __global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
@@ -747,7 +763,9 @@ __device__ __forceinline__ int64_t claim_item(BatchState *__restrict__ st, int *
     return it;
 }
 
-template <bool kMfma>
+enum class BatchKind { kPopcount, kMfmaI8, kMfmaFp4 };
+
+template <BatchKind kKind>
 __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
                                            const uint32_t *__restrict__ train,
                                            const PairEntry *__restrict__ pairs,
@@ -755,7 +773,8 @@ __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
                                            const int32_t *__restrict__ item_pair,
                                            BatchState *__restrict__ st, int k, float ratio,
                                            int32_t *__restrict__ idx, int32_t *__restrict__ dist,
-                                           uint8_t *__restrict__ accept, v4i (*tbuf)[kTileVec],
+                                           uint8_t *__restrict__ accept, void *tbuf,
+                                           const uint32_t *lut_train, const uint32_t *lut_query,
                                            int *slot, int n_pairs)
 {
     for (;;) {
@@ -766,15 +785,29 @@ __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
         const PairEntry e = pairs[p];
         const int qgroup = (int)(item - info[p].item_first);
         const int nt = (int)e.nt;
-        const int split_rows = max(kTileRows, (nt + kTileRows - 1) / kTileRows * kTileRows);
         const ItemOut out{nullptr, idx + e.out_first * k, dist + e.out_first * k,
                           accept ? accept + e.out_first : nullptr, k, ratio};
         const uint32_t *q = query + (size_t)e.query_first * kWords;
         const uint32_t *t = train + (size_t)(nt ? e.train_first : 0) * kWords;
-        if constexpr (kMfma)
-            mfma_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out, tbuf);
-        else
-            popcount_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out);
+        if constexpr (kKind == BatchKind::kMfmaFp4) {
+            // The pair's whole train range in ranges of at most 2^14 rows
+            // (the MXFP4 keys' index field), merged in registers.
+            uint64_t best[kFp4QueryBlocks][2];
+            fp4_init_best(best);
+            const int ranges = max(1, (nt + (int)kFp4MaxSplitRows - 1) / (int)kFp4MaxSplitRows);
+            for (int r = 0; r < ranges; ++r)
+                fp4_item<kFp4QueryBlocks>(q, (int)e.nq, t, nt, qgroup, r, (int)kFp4MaxSplitRows, best,
+                                          reinterpret_cast<uint4 (*)[kFp4TileVec]>(tbuf), lut_train,
+                                          lut_query);
+            fp4_store(best, (int)e.nq, nt, qgroup, 0, out);
+        } else {
+            const int split_rows = max(kTileRows, (nt + kTileRows - 1) / kTileRows * kTileRows);
+            if constexpr (kKind == BatchKind::kMfmaI8)
+                mfma_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out,
+                          reinterpret_cast<v4i (*)[kTileVec]>(tbuf));
+            else
+                popcount_item(q, (int)e.nq, t, nt, qgroup, 0, split_rows, out);
+        }
     }
 }
 
@@ -788,8 +821,25 @@ knn_batch_mfma_kernel(const uint32_t *__restrict__ query, const uint32_t *__rest
 {
     __shared__ v4i tbuf[2][kTileVec];
     __shared__ int slot;
-    batch_loop<true>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist, accept, tbuf,
-                     &slot, n_pairs);
+    batch_loop<BatchKind::kMfmaI8>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
+                                   accept, tbuf, nullptr, nullptr, &slot, n_pairs);
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+knn_batch_fp4_kernel(const uint32_t *__restrict__ query, const uint32_t *__restrict__ train,
+                     const PairEntry *__restrict__ pairs, int n_pairs,
+                     const PairInfo *__restrict__ info, const int32_t *__restrict__ item_pair,
+                     BatchState *__restrict__ st, int k, float ratio, int32_t *__restrict__ idx,
+                     int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
+{
+    __shared__ uint4 tbuf[2][kFp4TileVec];
+    __shared__ uint32_t lut_train[256], lut_query[256];
+    __shared__ int slot;
+    lut_train[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0x0u);
+    lut_query[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0xau);
+    __syncthreads();
+    batch_loop<BatchKind::kMfmaFp4>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
+                                    accept, tbuf, lut_train, lut_query, &slot, n_pairs);
 }
 
 __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
@@ -799,8 +849,8 @@ __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
     int32_t *__restrict__ idx, int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
 {
     __shared__ int slot;
-    batch_loop<false>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist, accept,
-                      nullptr, &slot, n_pairs);
+    batch_loop<BatchKind::kPopcount>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
+                                     accept, nullptr, nullptr, nullptr, &slot, n_pairs);
 }
 
 }  // namespace
@@ -842,9 +892,13 @@ hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream)
     hipLaunchKernelGGL(knn_batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a.info,
                        a.n_pairs, a.item_pair);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int blocks = a.num_cus * (a.mfma ? 2 : 8);
-    if (a.mfma)
+    const int blocks = a.num_cus * (a.kind == SplitKernel::kPopcount ? 8 : 2);
+    if (a.kind == SplitKernel::kMfmaI8)
         hipLaunchKernelGGL(knn_batch_mfma_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
+                           a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
+                           a.idx, a.dist, a.accept);
+    else if (a.kind == SplitKernel::kMfmaFp4)
+        hipLaunchKernelGGL(knn_batch_fp4_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
                            a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
                            a.idx, a.dist, a.accept);
     else

@@ -241,7 +241,7 @@ void default_tuning(latch_tuning *t)
 {
     std::memset(t, 0, sizeof *t);
     std::memset(t->path, LATCH_PATH_MFMA_FP4, sizeof t->path);
-    t->batch_path = LATCH_PATH_MFMA;
+    t->batch_path = LATCH_PATH_MFMA_FP4;
     t->mfma_groups_per_cu = 2;
     t->popcount_groups_per_cu = 8;
 }
@@ -309,7 +309,9 @@ BatchArgs batch_args(latch_handle h, uint8_t *ws, const uint32_t *query_dev, int
     a.accept = accept_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
-    a.mfma = path != LATCH_PATH_POPCOUNT;
+    a.kind = path == LATCH_PATH_POPCOUNT ? SplitKernel::kPopcount
+             : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
+                                           : SplitKernel::kMfmaI8;
     return a;
 }
 
@@ -541,11 +543,12 @@ int latch_get_tuning(latch_handle h, latch_tuning *out)
 int latch_set_tuning(latch_handle h, const latch_tuning *t)
 {
     if (!h || !t) return LATCH_EINVAL;
-    auto ok_path = [](int p) { return p == LATCH_PATH_MFMA || p == LATCH_PATH_POPCOUNT; };
+    auto ok_path = [](int p) {
+        return p == LATCH_PATH_MFMA || p == LATCH_PATH_POPCOUNT || p == LATCH_PATH_MFMA_FP4;
+    };
     for (int i = 0; i < 8; ++i)
         for (int j = 0; j < 8; ++j)
-            if (!ok_path(t->path[i][j]) && t->path[i][j] != LATCH_PATH_MFMA_FP4)
-                return fail(h, LATCH_ERANGE, "tuning path[%d][%d]", i, j);
+            if (!ok_path(t->path[i][j])) return fail(h, LATCH_ERANGE, "tuning path[%d][%d]", i, j);
     if (!ok_path(t->batch_path)) return fail(h, LATCH_ERANGE, "tuning batch_path");
     if (t->mfma_groups_per_cu < 1 || t->popcount_groups_per_cu < 1)
         return fail(h, LATCH_ERANGE, "tuning workgroup targets must be >= 1");
@@ -610,7 +613,10 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
     const BatchArgs a = batch_args(h, h->ws, query_dev, query_rows, train_dev, train_rows,
                                    pairs_dev, n_pairs, k, ratio, idx_dev, dist_dev, accept_dev,
                                    out_rows, path);
-    hipError_t e = timed_launch(h, a.mfma ? "knn_batch_mfma" : "knn_batch_popcount", stream,
+    const char *name = a.kind == SplitKernel::kPopcount  ? "knn_batch_popcount"
+                       : a.kind == SplitKernel::kMfmaFp4 ? "knn_batch_fp4"
+                                                         : "knn_batch_mfma";
+    hipError_t e = timed_launch(h, name, stream,
                                 [&] { return launch_knn_batch(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched knn launch");
 }

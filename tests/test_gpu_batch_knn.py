@@ -55,7 +55,7 @@ def check_pairs(torch, lat, D, rows, out_rows, k, ratio, path):
     return idx, dist, acc
 
 
-@pytest.mark.parametrize("path", ["mfma", "popcount"])
+@pytest.mark.parametrize("path", ["mfma", "fp4", "popcount"])
 def test_uneven_consecutive_pairs(torch_cuda, lat, path):
     g = np.random.default_rng(7)
     counts = [300, 0, 257, 1, 2, 511, 33, 1000, 640, 5]
@@ -72,7 +72,7 @@ def test_batch_equals_single_calls(torch_cuda, lat):
     counts = [700, 900, 650, 1200]
     D = synth.random_descriptors(g, sum(counts))
     rows, out_rows = consecutive_pairs(counts)
-    idx, dist, acc = check_pairs(torch_cuda, lat, D, rows, out_rows, 2, 0.8, "mfma")
+    idx, dist, acc = check_pairs(torch_cuda, lat, D, rows, out_rows, 2, 0.8, "auto")
     for qf, nq, tf, nt, of in rows:
         si, sd, sa = lat.knn(dev(torch_cuda, D[qf:qf + nq]), dev(torch_cuda, D[tf:tf + nt]))
         torch_cuda.cuda.synchronize()
@@ -127,4 +127,19 @@ def test_sfm_shaped_batch_sampled(torch_cuda, lat, triplets):
         assert np.array_equal(idx[of + sel], wi)
         assert np.array_equal(dist[of + sel], wd)
         assert np.array_equal(acc[of + sel], wa)
+    assert lat.check_errors(clear=True) == 0
+
+
+@pytest.mark.parametrize("path", ["fp4", "mfma"])
+def test_long_train_ranges(torch_cuda, lat, path):
+    """Pairs whose train range exceeds 2^14 rows: the MXFP4 batch matcher scans
+    such a range in pieces of 2^14 rows and merges them in registers; ties
+    across piece boundaries resolve to the lowest index."""
+    g = np.random.default_rng(12)
+    counts = [70, 16385, 300, 40000, 5]
+    D = synth.random_descriptors(g, sum(counts), 0.05)
+    D[70 + 16384] = D[70]                         # tie across the 2^14 boundary of pair 0
+    D[70 + 16385 + 300 + 20000] = D[70 + 16385 + 5]
+    rows, out_rows = consecutive_pairs(counts)
+    check_pairs(torch_cuda, lat, D, rows, out_rows, 2, 0.8, path)
     assert lat.check_errors(clear=True) == 0
