@@ -67,6 +67,12 @@ def _load():
         lib.oracle_knn.restype = None
         lib.oracle_num_threads.argtypes = []
         lib.oracle_num_threads.restype = i32
+        lib.oracle_fast_score.argtypes = [P, i32, i32, i32]
+        lib.oracle_fast_score.restype = i32
+        lib.oracle_orientation_bin.argtypes = [P, i32, i32, i32, P, P]
+        lib.oracle_orientation_bin.restype = i32
+        lib.oracle_detect.argtypes = [P, i32, i32, i32, i32, P, i64]
+        lib.oracle_detect.restype = i64
         lib.oracle_set_threads.argtypes = [i32]
         lib.oracle_set_threads.restype = None
         _lib = lib
@@ -76,6 +82,37 @@ def _load():
 def num_threads():
     """OpenMP threads used by extract() and knn()."""
     return int(_load().oracle_num_threads())
+
+
+DETECT_BORDER = 16
+ORIENT_RADIUS = 15
+
+
+def fast_score(img, x, y):
+    """FAST-9 score of pixel (x, y) (the circle must lie inside the image)."""
+    img = _image(img)
+    return int(_load().oracle_fast_score(_ptr(img), img.shape[1], int(x), int(y)))
+
+
+def orientation_bin(img, x, y):
+    """(bin, m10, m01): intensity-centroid orientation of pixel (x, y)."""
+    img = _image(img)
+    m10, m01 = ctypes.c_int64(), ctypes.c_int64()
+    b = _load().oracle_orientation_bin(_ptr(img), img.shape[1], int(x), int(y),
+                                       ctypes.byref(m10), ctypes.byref(m01))
+    return int(b), m10.value, m01.value
+
+
+def detect(img, threshold, max_kps=1 << 20):
+    """FAST-9 corners with suppression and orientation: (float32[n, 4] keypoints
+    in raster order, total count found)."""
+    img = _image(img)
+    kps = np.zeros((max_kps, 4), np.float32)
+    n = _load().oracle_detect(_ptr(img), img.shape[0], img.shape[1], img.shape[1], int(threshold),
+                              _ptr(kps), max_kps)
+    if n < 0:
+        raise MemoryError("oracle_detect")
+    return kps[:min(n, max_kps)].copy(), int(n)
 
 
 def set_threads(n):

@@ -267,6 +267,117 @@ void oracle_knn(const uint32_t *query, int64_t nq, const uint32_t *train, int64_
     }
 }
 
+/*
+ * Keypoint detection (Sec. 3.2: the paper detects FAST keypoints and uses
+ * their orientation; neither the FAST score, the suppression nor the
+ * orientation method is stated, so this file fixes them):
+ *
+ *   - FAST-9 segment test (Rosten and Drummond): the 16 pixels of the
+ *     radius-3 circle around p, clockwise from the top.  With c = I(p), the
+ *     score is the largest, over the 16 arcs of 9 consecutive circle pixels
+ *     and over both polarities, of the smallest difference on the arc
+ *     (I(q) - c for "brighter", c - I(q) for "darker").  p is a corner for
+ *     threshold t iff its score is > t, i.e. iff some arc of 9 is entirely
+ *     brighter than c + t or entirely darker than c - t.
+ *   - Only pixels at least DETECT_BORDER from every image edge are tested.
+ *     S(p) = score(p) for a corner there, 0 otherwise.  Suppression keeps p
+ *     iff S(p) > 0 and S(p) > S(q) for its 8 neighbours.
+ *   - Orientation: intensity-centroid moments m10 = sum dx I, m01 = sum dy I
+ *     over the disc dx^2 + dy^2 <= ORIENT_RADIUS^2 (y downwards, so angles
+ *     turn clockwise on screen, as in the resampling rule), angle bin
+ *     b = rne(atan2(m01, m10) * 4096 / 2 pi) mod 4096 in double, and the
+ *     keypoint angle b * 360 / 4096 degrees (exact in float), scale 1.
+ *   - Keypoints in raster order (y, then x).
+ */
+#define DETECT_BORDER 16
+#define ORIENT_RADIUS 15
+
+static const int fast_circle[16][2] = {
+    {0, -3}, {1, -3}, {2, -2}, {3, -1}, {3, 0}, {3, 1}, {2, 2}, {1, 3},
+    {0, 3}, {-1, 3}, {-2, 2}, {-3, 1}, {-3, 0}, {-3, -1}, {-2, -2}, {-1, -3}};
+
+/* FAST-9 score of pixel (x, y); the caller keeps the circle inside the image. */
+int oracle_fast_score(const uint8_t *img, int pitch, int x, int y)
+{
+    const int c = img[(int64_t)y * pitch + x];
+    int best = -256;
+    for (int polarity = 0; polarity < 2; ++polarity) {
+        int d[16];
+        for (int i = 0; i < 16; ++i) {
+            const int q = img[(int64_t)(y + fast_circle[i][1]) * pitch + x + fast_circle[i][0]];
+            d[i] = polarity == 0 ? q - c : c - q;
+        }
+        for (int k = 0; k < 16; ++k) {
+            int m = 256;
+            for (int j = 0; j < 9; ++j) {
+                const int v = d[(k + j) % 16];
+                if (v < m) m = v;
+            }
+            if (m > best) best = m;
+        }
+    }
+    return best;
+}
+
+/* Orientation bin of pixel (x, y) from its intensity centroid. */
+int oracle_orientation_bin(const uint8_t *img, int pitch, int x, int y, int64_t *m10_out,
+                           int64_t *m01_out)
+{
+    int64_t m10 = 0, m01 = 0;
+    for (int dy = -ORIENT_RADIUS; dy <= ORIENT_RADIUS; ++dy)
+        for (int dx = -ORIENT_RADIUS; dx <= ORIENT_RADIUS; ++dx) {
+            if (dx * dx + dy * dy > ORIENT_RADIUS * ORIENT_RADIUS) continue;
+            const int v = img[(int64_t)(y + dy) * pitch + x + dx];
+            m10 += (int64_t)dx * v;
+            m01 += (int64_t)dy * v;
+        }
+    if (m10_out) *m10_out = m10;
+    if (m01_out) *m01_out = m01;
+    const double a = atan2((double)m01, (double)m10);
+    return (int)((int64_t)rint(a * (4096.0 / (2.0 * 3.14159265358979323846))) & 4095);
+}
+
+/* Detect: writes up to max_kps keypoints (x, y, angle_deg, 1) in raster
+ * order to kps (float[max_kps][4]) and returns the number of corners found,
+ * which may exceed max_kps. */
+int64_t oracle_detect(const uint8_t *img, int height, int width, int pitch, int threshold,
+                      float *kps, int64_t max_kps)
+{
+    if (height < 2 * DETECT_BORDER + 1 || width < 2 * DETECT_BORDER + 1) return 0;
+    int *S = (int *)calloc((size_t)height * width, sizeof(int));
+    if (!S) return -1;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (int y = DETECT_BORDER; y < height - DETECT_BORDER; ++y)
+        for (int x = DETECT_BORDER; x < width - DETECT_BORDER; ++x) {
+            const int sc = oracle_fast_score(img, pitch, x, y);
+            S[(int64_t)y * width + x] = sc > threshold ? sc : 0;
+        }
+    int64_t n = 0;
+    for (int y = DETECT_BORDER; y < height - DETECT_BORDER; ++y)
+        for (int x = DETECT_BORDER; x < width - DETECT_BORDER; ++x) {
+            const int s0 = S[(int64_t)y * width + x];
+            if (s0 <= 0) continue;
+            int keep = 1;
+            for (int dy = -1; dy <= 1 && keep; ++dy)
+                for (int dx = -1; dx <= 1; ++dx)
+                    if ((dx || dy) && S[(int64_t)(y + dy) * width + x + dx] >= s0) {
+                        keep = 0;
+                        break;
+                    }
+            if (!keep) continue;
+            if (n < max_kps) {
+                const int b = oracle_orientation_bin(img, pitch, x, y, 0, 0);
+                kps[4 * n + 0] = (float)x;
+                kps[4 * n + 1] = (float)y;
+                kps[4 * n + 2] = (float)b * (360.0f / 4096.0f);
+                kps[4 * n + 3] = 1.0f;
+            }
+            ++n;
+        }
+    free(S);
+    return n;
+}
+
 /* Number of OpenMP threads the parallel loops above use. */
 int oracle_num_threads(void)
 {

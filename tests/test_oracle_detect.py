@@ -1,0 +1,113 @@
+"""Pins of the oracle's keypoint detector (FAST-9 score, suppression,
+intensity-centroid orientation) against independent definitions and closed
+forms: the segment test written out in numpy from a circle derived as the
+lattice points at distance [2.5, 3.5), single-dot and constant images, linear
+ramps with exactly known moments and angles, and quarter-turn invariance."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_03986_amd import synth
+
+
+def circle_offsets():
+    pts = [(dx, dy) for dy in range(-3, 4) for dx in range(-3, 4)
+           if 2.5 <= math.hypot(dx, dy) < 3.5]
+    pts.sort(key=lambda p: math.atan2(p[1], p[0]))        # cyclic order
+    assert len(pts) == 16
+    return pts
+
+
+def segment_test(img, x, y, t):
+    """True iff 9 cyclically consecutive circle pixels are all > c + t or all < c - t."""
+    c = int(img[y, x])
+    ring = [int(img[y + dy, x + dx]) for dx, dy in circle_offsets()]
+    for sign in (1, -1):
+        ok = [sign * (v - c) > t for v in ring]
+        for k in range(16):
+            if all(ok[(k + j) % 16] for j in range(9)):
+                return True
+    return False
+
+
+def test_score_is_the_largest_threshold_of_the_segment_test():
+    g = np.random.default_rng(5)
+    for trial in range(6):
+        img = synth.smoothed_noise(g, 40, 40) if trial % 2 else g.integers(0, 256, (40, 40)).astype(np.uint8)
+        for _ in range(60):
+            x, y = (int(v) for v in g.integers(3, 37, 2))
+            s = oracle.fast_score(img, x, y)
+            for t in (0, 5, 20, 40, 80, s - 1, s, s + 1):
+                if t < 0:
+                    continue
+                assert segment_test(img, x, y, t) == (s > t), (trial, x, y, t, s)
+
+
+def test_single_dot_and_constant_image():
+    img = np.full((64, 70), 30, np.uint8)
+    kps, n = oracle.detect(img, 10)
+    assert n == 0
+    img[40, 33] = 230
+    kps, n = oracle.detect(img, 10)
+    assert n == 1 and kps[0, 0] == 33 and kps[0, 1] == 40 and kps[0, 3] == 1.0
+    assert oracle.fast_score(img, 33, 40) == 200
+    kps, n = oracle.detect(img, 200)            # score must exceed the threshold
+    assert n == 0
+
+
+def disc():
+    r = oracle.ORIENT_RADIUS
+    return [(dx, dy) for dy in range(-r, r + 1) for dx in range(-r, r + 1) if dx * dx + dy * dy <= r * r]
+
+
+@pytest.mark.parametrize("ax,ay,bin_", [(1, 0, 0), (0, 1, 1024), (-1, 0, 2048), (0, -1, 3072),
+                                        (1, 1, 512), (-1, 1, 1536)])
+def test_orientation_of_ramps(ax, ay, bin_):
+    h = w = 64
+    yy, xx = np.mgrid[0:h, 0:w]
+    img = (128 + 2 * ax * (xx - 32) + 2 * ay * (yy - 32)).astype(np.uint8)
+    b, m10, m01 = oracle.orientation_bin(img, 32, 32)
+    d = disc()
+    want10 = sum(dx * int(img[32 + dy, 32 + dx]) for dx, dy in d)
+    want01 = sum(dy * int(img[32 + dy, 32 + dx]) for dx, dy in d)
+    assert (m10, m01) == (want10, want01)
+    assert m10 == 2 * ax * sum(dx * dx for dx, dy in d) and m01 == 2 * ay * sum(dy * dy for dx, dy in d)
+    assert b == bin_
+
+
+def test_orientation_matches_textbook_angle():
+    g = np.random.default_rng(9)
+    img = synth.smoothed_noise(g, 80, 80)
+    for _ in range(50):
+        x, y = (int(v) for v in g.integers(16, 64, 2))
+        b, m10, m01 = oracle.orientation_bin(img, x, y)
+        ang = math.degrees(math.atan2(m01, m10)) % 360.0
+        assert abs(((b * 360.0 / 4096.0 - ang) + 180.0) % 360.0 - 180.0) <= 360.0 / 4096.0 / 2 + 1e-9
+
+
+def test_quarter_turn_invariance():
+    g = np.random.default_rng(17)
+    n = 160
+    img = synth.smoothed_noise(g, n, n)
+    kps, cnt = oracle.detect(img, 20)
+    assert cnt > 200
+    rot = np.ascontiguousarray(np.rot90(img))             # rot[i][j] = img[j][n - 1 - i]
+    kr, cr = oracle.detect(rot, 20)
+    assert cr == cnt
+    bins = np.rint(kps[:, 2] * 4096.0 / 360.0).astype(int)
+    mapped = {(int(y), n - 1 - int(x), int((b - 1024) % 4096)) for (x, y, _, _), b in zip(kps, bins)}
+    got = {(int(x), int(y), int(np.rint(a * 4096.0 / 360.0)) % 4096) for x, y, a, _ in kr}
+    assert got == mapped
+
+
+def test_raster_order_and_truncation():
+    g = np.random.default_rng(21)
+    img = synth.smoothed_noise(g, 120, 200)
+    kps, n = oracle.detect(img, 15)
+    assert n > 100
+    order = kps[:, 1] * 10000 + kps[:, 0]
+    assert np.all(np.diff(order) > 0)
+    k5, n5 = oracle.detect(img, 15, max_kps=5)
+    assert n5 == n and np.array_equal(k5, kps[:5])
