@@ -149,6 +149,36 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
                         hipStream_t stream);
 
 /*
+ * Keypoint detection (Sec. 3.2: the paper extracts LATCH at FAST keypoints
+ * and their orientation; score, suppression and orientation method are
+ * not stated there and are fixed as follows).
+ *   - FAST-9: for the 16 pixels of the radius-3 circle around p and c the
+ *     value at p, score = the largest, over the 16 arcs of 9 consecutive
+ *     circle pixels and both polarities, of the smallest difference on the
+ *     arc (q - c brighter, c - q darker); p is a corner iff score > threshold.
+ *   - Only pixels at least 16 from every edge are tested.  Suppression keeps
+ *     a corner whose score exceeds that of every corner among its 8
+ *     neighbours (strictly).
+ *   - Orientation: m10 = sum dx I, m01 = sum dy I over the disc of radius 15
+ *     (y downwards); angle bin b = rne(atan2(m01, m10) * 4096 / 2 pi) mod
+ *     4096 in double; angle_deg = b * 360 / 4096 (exact, so extraction uses
+ *     bin b); scale 1.
+ *   img_dev:    u8, height x width, row stride pitch (limits as latch_extract).
+ *   threshold:  in [0, 255] (LATCH_ERANGE otherwise).
+ *   kps_dev:    latch_keypoint[max_kps]: the first max_kps keypoints in raster
+ *               order (y, then x).
+ *   n_kps_dev:  one int64 (device): the number of keypoints found, which may
+ *               exceed max_kps; pass it with max_kps to latch_extract_batch.
+ *   image_id_dev: int32[max_kps] or NULL: if given, image_index is written
+ *               for every keypoint written.
+ * Uses the handle's workspace (height * width + 12 * height bytes, grown as
+ * needed); images below 33 x 33 have no keypoints.
+ */
+int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                 int threshold, latch_keypoint *kps_dev, int64_t max_kps, int64_t *n_kps_dev,
+                 int32_t *image_id_dev, int32_t image_index, hipStream_t stream);
+
+/*
  * Brute-force k-NN under Hamming distance (Sec. 4, "Descriptor matching on the GPU").
  *   query_dev: uint32[nq][16], train_dev: uint32[nt][16] descriptors.
  *   k:         1 or 2 (LATCH_ERANGE otherwise).
@@ -288,7 +318,7 @@ int latch_set_tuning(latch_handle h, const latch_tuning *t);
  * kernel the handle launches is bracketed by two hipEventRecord calls on the
  * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops
  * recording).  latch_timing_read waits for the recorded events and returns,
- * for one kernel name ("extract", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge",
+ * for one kernel name ("extract", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge",
  * "knn_batch_mfma", "knn_batch_fp4", "knn_batch_popcount"; the batch names cover the whole
  * batched sequence), the number of launches recorded and their summed
  * duration in milliseconds.  Not for use under stream capture.

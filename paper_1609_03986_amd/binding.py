@@ -31,13 +31,14 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
                 -4: "LATCH_ERANGE"}
 
 # Every symbol include/latch.h declares.
-EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "hamming_knn",
+EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "latch_detect",
+           "hamming_knn",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
            "latch_get_tuning", "latch_set_tuning",
            "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
-KERNELS = ("extract", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge", "knn_batch_mfma",
+KERNELS = ("extract", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge", "knn_batch_mfma",
            "knn_batch_popcount")
 
 
@@ -72,6 +73,8 @@ def load_library():
     lib.latch_extract.restype = I
     lib.latch_extract_batch.argtypes = [P, P, I, P, P, I64, P, P, P]
     lib.latch_extract_batch.restype = I
+    lib.latch_detect.argtypes = [P, P, I, I, I, I, P, I64, P, P, I, P]
+    lib.latch_detect.restype = I
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
     lib.hamming_knn_batch.argtypes = [P, P, I64, P, I64, P, I, I, F, P, P, P, I64, I, P]
     lib.hamming_knn_batch.restype = I
@@ -177,6 +180,28 @@ def latch_extract(h, img, kps, desc=None, stream=None):
                                       _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
     _check(h, rc)
     return desc
+
+
+def latch_detect(h, img, threshold, max_kps, kps=None, n_kps=None, image_id=None, image_index=0,
+                 stream=None):
+    """FAST-9 keypoints with orientation; returns (kps float32 [max_kps, 4],
+    n_kps int64 [1] on the device: the number found, which may exceed max_kps)."""
+    import torch
+    if img.dim() != 2:
+        raise ValueError("img must be 2-D")
+    dev = img.device
+    if kps is None:
+        kps = torch.empty((max_kps, 4), dtype=torch.float32, device=dev)
+    if n_kps is None:
+        n_kps = torch.empty((1,), dtype=torch.int64, device=dev)
+    H, W = img.shape
+    idp = _dev(image_id, torch.int32, "image_id") if image_id is not None else None
+    rc = load_library().latch_detect(h, _dev(img, torch.uint8, "img"), H, W, img.stride(0),
+                                     int(threshold), _dev(kps, torch.float32, "kps"), int(max_kps),
+                                     _dev(n_kps, torch.int64, "n_kps"), idp, int(image_index),
+                                     _stream_ptr(stream))
+    _check(h, rc)
+    return kps, n_kps
 
 
 IMAGE_ENTRY_BYTES = 24
@@ -393,6 +418,9 @@ class Latch:
 
     def extract(self, img, kps, desc=None, stream=None):
         return latch_extract(self.h, img, kps, desc, stream)
+
+    def detect(self, img, threshold, max_kps, **kw):
+        return latch_detect(self.h, img, threshold, max_kps, **kw)
 
     def extract_batch(self, table, n_images, image_id, kps, desc=None, n_kps=None, stream=None):
         return latch_extract_batch(self.h, table, n_images, image_id, kps, desc, n_kps, stream)

@@ -77,6 +77,26 @@ struct ExtractArgs {
 
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
 
+// Keypoint detection (FAST-9, suppression, intensity-centroid orientation).
+constexpr int kDetectBorder = 16;
+constexpr int kOrientRadius = 15;
+
+struct DetectArgs {
+    const uint8_t *img;
+    int height, width, pitch, threshold;
+    uint8_t *score;           // workspace: height * width bytes
+    int32_t *row_count;       // workspace: height
+    int64_t *row_first;       // workspace: height
+    float4 *kps;
+    int64_t max_kps;
+    int64_t *n_kps;           // device: corners found
+    int32_t *image_id;        // optional
+    int32_t image_index;
+    int num_cus;
+};
+
+hipError_t launch_detect(const DetectArgs &a, hipStream_t stream);
+
 struct KnnPlan {
     int64_t nq, nt;
     int64_t split_rows;       // multiple of kTileRows, <= kMaxSplitRows

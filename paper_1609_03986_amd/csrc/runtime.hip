@@ -483,6 +483,46 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
 }
 
+int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                 int threshold, latch_keypoint *kps_dev, int64_t max_kps, int64_t *n_kps_dev,
+                 int32_t *image_id_dev, int32_t image_index, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (!img_dev || !n_kps_dev || (max_kps > 0 && !kps_dev))
+        return fail(h, LATCH_EINVAL, "null buffer");
+    if (height < 1 || width < 1 || pitch < width || height >= (1 << 23) || pitch >= (1 << 23) ||
+        (int64_t)height * pitch > (int64_t)0x7fffffff)
+        return fail(h, LATCH_EINVAL, "image %d x %d, pitch %d outside the limits", height, width,
+                    pitch);
+    if (threshold < 0 || threshold > 255)
+        return fail(h, LATCH_ERANGE, "threshold %d (must be in [0, 255])", threshold);
+    if (max_kps < 0 || max_kps > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "max_kps = %lld", (long long)max_kps);
+    const size_t score_bytes = align_up((size_t)height * width, 256);
+    const size_t count_bytes = align_up((size_t)height * sizeof(int32_t), 256);
+    const size_t first_bytes = align_up((size_t)height * sizeof(int64_t), 256);
+    const int rc = ensure_workspace(h, score_bytes + count_bytes + first_bytes);
+    if (rc != LATCH_OK) return rc;
+    DetectArgs a;
+    a.img = img_dev;
+    a.height = height;
+    a.width = width;
+    a.pitch = pitch;
+    a.threshold = threshold;
+    a.score = h->ws;
+    a.row_count = reinterpret_cast<int32_t *>(h->ws + score_bytes);
+    a.row_first = reinterpret_cast<int64_t *>(h->ws + score_bytes + count_bytes);
+    a.kps = reinterpret_cast<float4 *>(kps_dev);
+    a.max_kps = max_kps;
+    a.n_kps = n_kps_dev;
+    a.image_id = image_id_dev;
+    a.image_index = image_index;
+    a.num_cus = h->num_cus;
+    const hipError_t e = timed_launch(h, "detect", stream, [&] { return launch_detect(a, stream); });
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "detect launch");
+}
+
 int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32_t *train_dev,
                 int64_t nt, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
                 uint8_t *accept_dev, int path, hipStream_t stream)

@@ -111,3 +111,51 @@ def test_raster_order_and_truncation():
     assert np.all(np.diff(order) > 0)
     k5, n5 = oracle.detect(img, 15, max_kps=5)
     assert n5 == n and np.array_equal(k5, kps[:5])
+
+
+def test_orientation_bin_does_not_depend_on_last_bits_of_atan2():
+    """The moments are integers of magnitude at most M, so their angle keeps a
+    distance from every bin boundary (2k + 1) pi / 4096 that is far above the
+    error of a double atan2 and product: any atan2 accurate to a few ulp gives
+    the same bin.  The closest approach is found from the continued fraction of
+    tan of each boundary in the first octant (the boundaries are symmetric
+    under reflection in the axes and the diagonal), whose convergents and
+    largest admissible semiconvergents are the best approximations p / q with
+    q <= M."""
+    mpmath = pytest.importorskip("mpmath")
+    mpmath.mp.dps = 60
+    r = oracle.ORIENT_RADIUS
+    M = 255 * sum(abs(dx) for dy in range(-r, r + 1) for dx in range(-r, r + 1)
+                  if dx * dx + dy * dy <= r * r)
+    C = mpmath.mpf(4096) / (2 * mpmath.pi)
+    worst = mpmath.mpf(1)
+    for k in range(512):                          # boundaries in (0, pi / 4)
+        t = mpmath.tan((2 * k + 1) * mpmath.pi / 4096)
+        cands = []
+        p0, q0, p1, q1 = 0, 1, 1, 0               # convergents p_{n-1}/q_{n-1}, p_n/q_n
+        x = t
+        while True:
+            a = int(mpmath.floor(x))
+            p2, q2 = a * p1 + p0, a * q1 + q0
+            if q2 > M:
+                j = (M - q0) // q1                # largest semiconvergent within M
+                if j >= 1:
+                    cands.append((j * p1 + p0, j * q1 + q0))
+                break
+            cands.append((p2, q2))
+            p0, q0, p1, q1 = p1, q1, p2, q2
+            frac = x - a
+            if frac == 0:
+                break
+            x = 1 / frac
+        for p, q in cands:
+            if q == 0:
+                continue
+            d = abs(mpmath.atan(mpmath.mpf(p) / q) * C - (k + mpmath.mpf(1) / 2))
+            worst = min(worst, d)
+    # Error of the computed rint argument for |atan2| <= pi: atan2 within 4
+    # ulp (of pi: 2^-51 each), the double constant 4096 / 2 pi and the product
+    # each rounded (relative 2^-53 of at most 2048).
+    err = 4 * 2.0 ** -51 * float(C) + 2 * 2048 * 2.0 ** -53
+    assert M < 1 << 21
+    assert worst > 2 * err, (float(worst), err)
