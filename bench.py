@@ -9,7 +9,8 @@ Inputs are resident in HBM before the timed region starts.
 
 Prints one JSON line.  `value` is descriptors extracted and matched per
 second for the whole step (20,000 descriptors per step).  Extra fields give
-the component rates (extraction desc/s, matching pairs/s per path), step
+the component rates (extraction desc/s, matching pairs/s per path,
+FAST detection of both images), step
 latency percentiles, per-kernel durations from HIP events recorded by the
 library on its launch stream, the roofline of the dominant kernel and the
 CPU oracle baseline.
@@ -43,6 +44,7 @@ PEAK_DOT4_TOPS = CUS * LANES * CLOCK_GHZ * 8 / 1000.0   # 314.6
 # differences x 3 integer ops; per matched pair, the 512 MACs of a.b.
 EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 3                  # sub, mul, add per squared difference
 MATCH_OPS_PER_PAIR = 512 * 2                             # 512 MACs of a.b
+DETECT_THRESHOLD = 20                                    # FAST threshold of the detection component
 
 
 def parse():
@@ -187,6 +189,40 @@ def main():
         match_kernel_ms[path] = total / max(n, 1)
         lat.timing(False)
 
+    # --- Keypoint detection (FAST-9, suppression, orientation) of both images,
+    # appended into one array with image ids. ---
+    det_cap = 1 << 17
+    det_kps = torch.empty((det_cap, 4), dtype=torch.float32, device=dev)
+    det_ids = torch.empty((det_cap,), dtype=torch.int32, device=dev)
+    det_n = torch.zeros((1,), dtype=torch.int64, device=dev)
+
+    def detect_both():
+        det_n.zero_()
+        lat.detect(img_q, DETECT_THRESHOLD, det_cap, kps=det_kps, n_kps=det_n, image_id=det_ids,
+                   image_index=0)
+        lat.detect(img_t, DETECT_THRESHOLD, det_cap, kps=det_kps, n_kps=det_n, image_id=det_ids,
+                   image_index=1)
+
+    d_wall, _ = timed_loop(detect_both, args.steps, 2)
+    n_found = int(det_n.item())
+    lat.timing(True)
+    for _ in range(args.steps):
+        detect_both()
+    torch.cuda.synchronize()
+    n_det, det_total = lat.timing_read("detect")
+    lat.timing(False)
+    det_ms = det_total / max(n_det, 1)
+    image_bytes = img_q.numel() + img_t.numel()
+    # Algorithmic HBM bytes per image: the image read once, 20 bytes per
+    # keypoint written (keypoint and image id).
+    det_bytes = (image_bytes + 20 * n_found) / 2
+    detection = {"threshold": DETECT_THRESHOLD, "keypoints_per_step": n_found,
+                 "images_per_s": 2 / (d_wall / args.steps),
+                 "avg_ms_per_image": det_ms,
+                 "roofline": {"bound": "hbm", "achieved": det_bytes / (det_ms * 1e-3) / 1e9,
+                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                              "frac": det_bytes / (det_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}}
+
     # --- The same step with the inputs starting in pinned host memory and the
     # results copied back (PCIe-inclusive; not the headline value). ---
     h_img_q = torch.from_numpy(w["query_image"]).pin_memory()
@@ -274,7 +310,8 @@ def main():
         "components": {"extract_desc_per_s": extract_desc_s,
                        "pcie_inclusive_desc_per_s": pcie_desc_s,
                        "match_pairs_per_s": match_rates,
-                       "match_kernel_avg_ms": match_kernel_ms},
+                       "match_kernel_avg_ms": match_kernel_ms,
+                       "detection": detection},
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

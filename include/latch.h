@@ -165,14 +165,19 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
  *     bin b); scale 1.
  *   img_dev:    u8, height x width, row stride pitch (limits as latch_extract).
  *   threshold:  in [0, 255] (LATCH_ERANGE otherwise).
- *   kps_dev:    latch_keypoint[max_kps]: the first max_kps keypoints in raster
- *               order (y, then x).
- *   n_kps_dev:  one int64 (device): the number of keypoints found, which may
- *               exceed max_kps; pass it with max_kps to latch_extract_batch.
+ *   kps_dev:    latch_keypoint[max_kps].  The image's keypoints are appended
+ *               in raster order (y, then x) after the n0 already there, as far
+ *               as max_kps allows.
+ *   n_kps_dev:  one int64 (device), in/out: n0 on entry (zero for a fresh
+ *               array; a negative value is taken as zero), n0 plus the number of keypoints found on exit, which
+ *               may exceed max_kps.  Detecting several images in turn into
+ *               one array, then latch_extract_batch with this count, runs
+ *               detection and extraction with no host round trip.
  *   image_id_dev: int32[max_kps] or NULL: if given, image_index is written
  *               for every keypoint written.
- * Uses the handle's workspace (height * width + 12 * height bytes, grown as
- * needed); images below 33 x 33 have no keypoints.
+ * Uses the handle's workspace (8 * height * ceil(width / 64) + 8 * height
+ * bytes, grown as needed); images below 33 x 33 have no keypoints.  Calls that share a
+ * handle or a count must be ordered (one stream).
  */
 int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
                  int threshold, latch_keypoint *kps_dev, int64_t max_kps, int64_t *n_kps_dev,

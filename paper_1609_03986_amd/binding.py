@@ -184,8 +184,9 @@ def latch_extract(h, img, kps, desc=None, stream=None):
 
 def latch_detect(h, img, threshold, max_kps, kps=None, n_kps=None, image_id=None, image_index=0,
                  stream=None):
-    """FAST-9 keypoints with orientation; returns (kps float32 [max_kps, 4],
-    n_kps int64 [1] on the device: the number found, which may exceed max_kps)."""
+    """FAST-9 keypoints with orientation, appended to kps after the n_kps[0]
+    already there; returns (kps float32 [max_kps, 4], n_kps int64 [1] on the
+    device: the new total, which may exceed max_kps).  A new n_kps starts at 0."""
     import torch
     if img.dim() != 2:
         raise ValueError("img must be 2-D")
@@ -193,7 +194,7 @@ def latch_detect(h, img, threshold, max_kps, kps=None, n_kps=None, image_id=None
     if kps is None:
         kps = torch.empty((max_kps, 4), dtype=torch.float32, device=dev)
     if n_kps is None:
-        n_kps = torch.empty((1,), dtype=torch.int64, device=dev)
+        n_kps = torch.zeros((1,), dtype=torch.int64, device=dev)
     H, W = img.shape
     idp = _dev(image_id, torch.int32, "image_id") if image_id is not None else None
     rc = load_library().latch_detect(h, _dev(img, torch.uint8, "img"), H, W, img.stride(0),

@@ -84,15 +84,14 @@ constexpr int kOrientRadius = 15;
 struct DetectArgs {
     const uint8_t *img;
     int height, width, pitch, threshold;
-    uint8_t *score;           // workspace: height * width bytes
-    int32_t *row_count;       // workspace: height
-    int64_t *row_first;       // workspace: height
+    uint64_t *masks;          // workspace: survivor mask per (row, 64-column tile)
+    int64_t *row_first;       // workspace: height (absolute output slot of each row)
+    int64_t *base;            // workspace: the count on entry
     float4 *kps;
     int64_t max_kps;
-    int64_t *n_kps;           // device: corners found
+    int64_t *n_kps;           // device, in/out: keypoints already in kps, then the new total
     int32_t *image_id;        // optional
     int32_t image_index;
-    int num_cus;
 };
 
 hipError_t launch_detect(const DetectArgs &a, hipStream_t stream);

@@ -499,10 +499,9 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
         return fail(h, LATCH_ERANGE, "threshold %d (must be in [0, 255])", threshold);
     if (max_kps < 0 || max_kps > LATCH_MAX_ROWS)
         return fail(h, LATCH_EINVAL, "max_kps = %lld", (long long)max_kps);
-    const size_t score_bytes = align_up((size_t)height * width, 256);
-    const size_t count_bytes = align_up((size_t)height * sizeof(int32_t), 256);
+    const size_t mask_bytes = align_up((size_t)height * ((width + 63) / 64) * sizeof(uint64_t), 256);
     const size_t first_bytes = align_up((size_t)height * sizeof(int64_t), 256);
-    const int rc = ensure_workspace(h, score_bytes + count_bytes + first_bytes);
+    const int rc = ensure_workspace(h, mask_bytes + first_bytes + sizeof(int64_t));
     if (rc != LATCH_OK) return rc;
     DetectArgs a;
     a.img = img_dev;
@@ -510,15 +509,14 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
     a.width = width;
     a.pitch = pitch;
     a.threshold = threshold;
-    a.score = h->ws;
-    a.row_count = reinterpret_cast<int32_t *>(h->ws + score_bytes);
-    a.row_first = reinterpret_cast<int64_t *>(h->ws + score_bytes + count_bytes);
+    a.masks = reinterpret_cast<uint64_t *>(h->ws);
+    a.row_first = reinterpret_cast<int64_t *>(h->ws + mask_bytes);
+    a.base = reinterpret_cast<int64_t *>(h->ws + mask_bytes + first_bytes);
     a.kps = reinterpret_cast<float4 *>(kps_dev);
     a.max_kps = max_kps;
     a.n_kps = n_kps_dev;
     a.image_id = image_id_dev;
     a.image_index = image_index;
-    a.num_cus = h->num_cus;
     const hipError_t e = timed_launch(h, "detect", stream, [&] { return launch_detect(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "detect launch");
 }

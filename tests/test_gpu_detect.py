@@ -111,29 +111,54 @@ def test_bad_arguments(torch_cuda, lat):
 
 
 def test_detect_then_batched_extract(torch_cuda, lat, triplets):
-    """Two images detected into one keypoint array with image ids, the device
-    count handed to batched extraction, descriptors equal to the oracle's."""
+    """Three images detected in turn into one keypoint array (appended, with
+    image ids), the device count handed to batched extraction: no host round
+    trip; keypoints and descriptors equal to the oracle's."""
     from paper_1609_03986_amd.binding import image_table
     torch = torch_cuda
     g = np.random.default_rng(6)
-    imgs = [synth.smoothed_noise(g, 240, 320), synth.smoothed_noise(g, 200, 300)]
+    imgs = [synth.smoothed_noise(g, 240, 320), synth.smoothed_noise(g, 200, 300),
+            synth.smoothed_noise(g, 90, 150)]
     dimgs = [torch.from_numpy(im).cuda() for im in imgs]
-    cap = 4000
-    kps = torch.tensor([[50.0, 50.0, 0.0, 1.0]], device="cuda").repeat(2 * cap, 1)   # rows past the counts
-    ids = torch.zeros((2 * cap,), dtype=torch.int32, device="cuda")
-    counts = []
+    cap = 12000
+    kps = torch.tensor([[50.0, 50.0, 0.0, 1.0]], device="cuda").repeat(cap, 1)
+    ids = torch.full((cap,), -1, dtype=torch.int32, device="cuda")
+    n = torch.zeros((1,), dtype=torch.int64, device="cuda")
     for i, d in enumerate(dimgs):
-        _, n = lat.detect(d, 20, cap, kps=kps[i * cap:(i + 1) * cap], image_id=ids[i * cap:(i + 1) * cap],
-                          image_index=i)
-        counts.append(n)
-    desc = lat.extract_batch(image_table(dimgs), 2, ids, kps)
+        lat.detect(d, 20, cap, kps=kps, n_kps=n, image_id=ids, image_index=i)
+    desc = torch.zeros((cap, 16), dtype=torch.int32, device="cuda")
+    lat.extract_batch(image_table(dimgs), 3, ids, kps, desc, n_kps=n)
     torch.cuda.synchronize()
-    D = desc.cpu().numpy().view(np.uint32)
-    K = kps.cpu().numpy()
+    D, K, I = desc.cpu().numpy().view(np.uint32), kps.cpu().numpy(), ids.cpu().numpy()
+    first = 0
     for i, im in enumerate(imgs):
         want_k, wn = oracle.detect(im, 20)
-        assert int(counts[i].item()) == wn and 0 < wn <= cap
-        assert np.array_equal(K[i * cap:i * cap + wn], want_k)
+        assert wn > 0
+        sl = slice(first, first + wn)
+        assert np.array_equal(K[sl], want_k) and np.all(I[sl] == i)
         want_d, _ = oracle.extract(im, want_k, triplets)
-        assert np.array_equal(D[i * cap:i * cap + wn], want_d)
+        assert np.array_equal(D[sl], want_d)
+        first += wn
+    assert int(n.item()) == first < cap
+    assert np.all(D[first:] == 0) and np.all(I[first:] == -1)
     assert lat.check_errors(clear=True) == 0
+
+
+def test_append_past_capacity(torch_cuda, lat):
+    """Appending to an array that fills up: the keypoints that fit are written,
+    the count keeps the full total."""
+    torch = torch_cuda
+    g = np.random.default_rng(8)
+    a, b = synth.smoothed_noise(g, 150, 200), synth.smoothed_noise(g, 160, 180)
+    ka, na = oracle.detect(a, 12)
+    kb, nb = oracle.detect(b, 12)
+    cap = na + nb // 2
+    kps = torch.zeros((cap, 4), dtype=torch.float32, device="cuda")
+    n = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    lat.detect(torch.from_numpy(a).cuda(), 12, cap, kps=kps, n_kps=n)
+    lat.detect(torch.from_numpy(b).cuda(), 12, cap, kps=kps, n_kps=n)
+    lat.detect(torch.from_numpy(a).cuda(), 12, cap, kps=kps, n_kps=n)    # nothing fits
+    torch.cuda.synchronize()
+    assert int(n.item()) == 2 * na + nb
+    K = kps.cpu().numpy()
+    assert np.array_equal(K[:na], ka) and np.array_equal(K[na:], kb[:cap - na])
