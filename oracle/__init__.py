@@ -75,6 +75,15 @@ def _load():
         lib.oracle_detect.restype = i64
         lib.oracle_set_threads.argtypes = [i32]
         lib.oracle_set_threads.restype = None
+        lib.oracle_sample_window_geom.argtypes = [P, i32, i32, i32, ctypes.c_float, ctypes.c_float,
+                                                  ctypes.c_float, ctypes.c_float, P, P, i32, P]
+        lib.oracle_sample_window_geom.restype = ctypes.c_uint
+        lib.oracle_triplet_distances_weighted.argtypes = [P, i32, i32, P, P, P, P]
+        lib.oracle_triplet_distances_weighted.restype = None
+        lib.oracle_triplets_valid_geom.argtypes = [P, i32, i32]
+        lib.oracle_triplets_valid_geom.restype = i32
+        lib.oracle_extract_geom.argtypes = [P, i32, i32, i32, P, i64, P, i32, i32, P, P]
+        lib.oracle_extract_geom.restype = ctypes.c_uint
         _lib = lib
     return _lib
 
@@ -190,6 +199,58 @@ def extract(img, kps, triplets):
     desc = np.zeros((n, WORDS), np.uint32)
     f = _load().oracle_extract(_ptr(img), img.shape[0], img.shape[1], img.shape[1],
                                _ptr(kps), n, _ptr(trip), _ptr(desc))
+    return desc, int(f)
+
+
+def _weights(weights, patch):
+    if weights is None:
+        return np.ones((patch, patch), np.uint8)
+    w = np.ascontiguousarray(np.asarray(weights, np.uint8).reshape(patch, patch))
+    return w
+
+
+def sample_window_geom(img, x, y, angle_deg=0.0, scale=1.0, window=64):
+    """Rule R with a window of side `window`: (uint8 tile, flag)."""
+    img = _image(img)
+    c, s = rotation_table()
+    tile = np.zeros((window, window), np.uint8)
+    f = _load().oracle_sample_window_geom(_ptr(img), img.shape[0], img.shape[1], img.shape[1],
+                                          float(x), float(y), float(angle_deg), float(scale),
+                                          _ptr(c), _ptr(s), int(window), _ptr(tile))
+    return tile, int(f)
+
+
+def triplet_distances_weighted(tile, triplet, patch=8, weights=None):
+    """Weighted distances (S1, S2) of one triplet on a square tile (Sec. 3.2)."""
+    tile = np.ascontiguousarray(tile, dtype=np.uint8)
+    win = tile.shape[0]
+    trip = np.ascontiguousarray(np.asarray(triplet, np.uint8).reshape(6))
+    w = _weights(weights, patch)
+    s1 = ctypes.c_int64()
+    s2 = ctypes.c_int64()
+    _load().oracle_triplet_distances_weighted(_ptr(tile), win, int(patch), _ptr(w), _ptr(trip),
+                                              ctypes.byref(s1), ctypes.byref(s2))
+    return s1.value, s2.value
+
+
+def triplets_valid_geom(triplets, window, patch):
+    trip = np.ascontiguousarray(np.asarray(triplets, np.uint8).reshape(TRIPLETS, 3, 2))
+    return bool(_load().oracle_triplets_valid_geom(_ptr(trip), int(window), int(patch)))
+
+
+def extract_geom(img, kps, triplets, window=64, patch=8, weights=None):
+    """Descriptors with window side `window`, patch side `patch` and integer
+    weights[patch][patch] (None: all ones), and the OR of the flags."""
+    img = _image(img)
+    kps = _keypoints(kps)
+    trip = np.ascontiguousarray(np.asarray(triplets, np.uint8).reshape(TRIPLETS, 3, 2))
+    if not _load().oracle_triplets_valid_geom(_ptr(trip), int(window), int(patch)):
+        raise ValueError("every patch must lie inside the window")
+    w = _weights(weights, patch)
+    n = kps.shape[0]
+    desc = np.zeros((n, WORDS), np.uint32)
+    f = _load().oracle_extract_geom(_ptr(img), img.shape[0], img.shape[1], img.shape[1], _ptr(kps), n,
+                                    _ptr(trip), int(window), int(patch), _ptr(w), _ptr(desc))
     return desc, int(f)
 
 

@@ -20,6 +20,9 @@
  *     window size used here (48), the scale handling or the rounding; this
  *     file fixes them as "rule R" (see oracle_sample_window below), written
  *     out step by step.
+ *   - Sec. 3.2 "Weighing pixels in LATCH patches": the CLATCH geometry (64 x 64
+ *     windows, 8 x 8 patches) with an integer weight per patch pixel
+ *     (oracle_extract_geom).
  *   - Sec. 4 "Descriptor matching on the GPU": exhaustive (brute-force)
  *     Hamming matching.  k = 2 nearest neighbours, ties to the lowest train
  *     index, ratio test d1 < ratio * d2 evaluated exactly.
@@ -217,6 +220,120 @@ unsigned oracle_extract(const uint8_t *img, int height, int width, int pitch,
         } else {
             oracle_describe_tile(tile, triplets, desc + OR_WORDS * p);
         }
+    }
+    return flags;
+}
+
+/* ------------------------------------------------------------------------ */
+/* The paper's CLATCH geometry and per-pixel patch weights (Sec. 3.2).       */
+/* ------------------------------------------------------------------------ */
+/*
+ * Sec. 3.2 extracts CLATCH from 64 x 64 windows with 8 x 8 patches, and lets
+ * each patch pixel carry an integer weight ("Weighing pixels in LATCH
+ * patches"): zero weights on one row and one column of the 8 x 8 patch give
+ * the original 7 x 7 LATCH, and Gaussian weights are suggested.  The
+ * functions below generalise the window side (win, even) and the patch side
+ * (k), and replace Eq. 1's plain sums by weighted ones:
+ *
+ *   S_j = sum over (a, b) in [0, k)^2 of w[a][b] * (A[a][b] - P_j[a][b])^2,
+ *   bit = [S_1 > S_2],
+ *
+ * where the patch of a triplet centre (r, c) has its top-left pixel at
+ * (r - k/2, c - k/2) (for k = 7 that is the 7 x 7 patch centred on (r, c);
+ * for k = 8 the centre is the pixel right and below the middle).  Rule R is
+ * unchanged except that window pixel (i, j) sits at (j - win/2, i - win/2).
+ */
+unsigned oracle_sample_window_geom(const uint8_t *img, int height, int width, int pitch,
+                                   float x, float y, float angle_deg, float scale,
+                                   const int16_t *cos_q14, const int16_t *sin_q14, int win,
+                                   uint8_t *tile)
+{
+    if (!isfinite(x) || !isfinite(y) || !isfinite(angle_deg) || !isfinite(scale))
+        return OR_FLAG_BAD_KEYPOINT;
+    if (fabs((double)x) > 16777216.0 || fabs((double)y) > 16777216.0)
+        return OR_FLAG_BAD_KEYPOINT;
+    if (fabs((double)angle_deg) > 1.0e6)
+        return OR_FLAG_BAD_KEYPOINT;
+    int64_t sq = (int64_t)rint((double)scale * 256.0);
+    if (sq < 1 || sq > 1024)
+        return OR_FLAG_BAD_KEYPOINT;
+    int64_t cx = (int64_t)floor((double)x + 0.5);
+    int64_t cy = (int64_t)floor((double)y + 0.5);
+    int64_t braw = (int64_t)rint((double)angle_deg * (4096.0 / 360.0));
+    int64_t b = ((braw % OR_BINS) + OR_BINS) % OR_BINS;
+    int64_t c = cos_q14[b], s = sin_q14[b];
+    int half = win / 2;
+    for (int i = 0; i < win; ++i)
+        for (int j = 0; j < win; ++j) {
+            int64_t u = j - half, v = i - half;
+            int64_t X = clamp64(cx + round_q22(sq * (c * u - s * v)), 0, width - 1);
+            int64_t Y = clamp64(cy + round_q22(sq * (s * u + c * v)), 0, height - 1);
+            tile[i * win + j] = img[Y * (int64_t)pitch + X];
+        }
+    return 0;
+}
+
+/* Weighted patch distances of one triplet on a win x win tile. */
+void oracle_triplet_distances_weighted(const uint8_t *tile, int win, int k, const uint8_t *weights,
+                                       const uint8_t *trip, int64_t *dist1, int64_t *dist2)
+{
+    int top[3], left[3];
+    for (int p = 0; p < 3; ++p) {
+        top[p] = trip[2 * p] - k / 2;
+        left[p] = trip[2 * p + 1] - k / 2;
+    }
+    int64_t s1 = 0, s2 = 0;
+    for (int a = 0; a < k; ++a)
+        for (int b = 0; b < k; ++b) {
+            int64_t w = weights[a * k + b];
+            int64_t A = tile[(top[0] + a) * win + left[0] + b];
+            int64_t P = tile[(top[1] + a) * win + left[1] + b];
+            int64_t Q = tile[(top[2] + a) * win + left[2] + b];
+            s1 += w * (A - P) * (A - P);
+            s2 += w * (A - Q) * (A - Q);
+        }
+    *dist1 = s1;
+    *dist2 = s2;
+}
+
+/* 1 if every patch of every triplet lies inside the win x win tile. */
+int oracle_triplets_valid_geom(const uint8_t *triplets, int win, int k)
+{
+    for (int i = 0; i < OR_T * 6; ++i) {
+        int first = triplets[i] - k / 2;
+        if (first < 0 || first + k > win)
+            return 0;
+    }
+    return 1;
+}
+
+/* Extraction with window side win, patch side k and weights[k][k]. */
+unsigned oracle_extract_geom(const uint8_t *img, int height, int width, int pitch,
+                             const float *kps, int64_t n, const uint8_t *triplets, int win, int k,
+                             const uint8_t *weights, uint32_t *desc)
+{
+    int16_t cos_q14[OR_BINS], sin_q14[OR_BINS];
+    oracle_rotation_table(cos_q14, sin_q14);
+    unsigned flags = 0;
+#pragma omp parallel for schedule(dynamic, 16) reduction(| : flags)
+    for (int64_t p = 0; p < n; ++p) {
+        uint8_t *tile = (uint8_t *)malloc((size_t)win * win);
+        const float *kp = kps + 4 * p;
+        uint32_t *d = desc + OR_WORDS * p;
+        memset(d, 0, OR_WORDS * sizeof(uint32_t));
+        unsigned f = oracle_sample_window_geom(img, height, width, pitch, kp[0], kp[1], kp[2],
+                                               kp[3], cos_q14, sin_q14, win, tile);
+        if (f) {
+            flags |= f;
+        } else {
+            for (int t = 0; t < OR_T; ++t) {
+                int64_t s1, s2;
+                oracle_triplet_distances_weighted(tile, win, k, weights, triplets + 6 * t, &s1, &s2);
+                if (s1 > s2)
+                    d[t / 32] |= (uint32_t)1 << (t % 32);
+            }
+        }
+        free(tile);
     }
     return flags;
 }

@@ -51,6 +51,44 @@ def triplet_table(seed_stream=9):
     return out
 
 
+def triplet_table_geom(window=64, patch=8, seed_stream=10):
+    """512 triplets for a window of side `window` and patches of side `patch`:
+    centres uniform over the positions whose patch (top-left at centre -
+    patch // 2) lies inside the window, i.e. [patch // 2, window - patch + patch // 2].
+    Seeded uniform triplets stand in for the learned table; triplets with two
+    equal centres are redrawn.  Returns uint8 [512, 3, 2]."""
+    lo, hi = patch // 2, window - patch + patch // 2
+    g = np.random.Generator(np.random.PCG64(BASE_SEED + seed_stream))
+    out = np.zeros((TRIPLETS, 3, 2), np.uint8)
+    t = 0
+    while t < TRIPLETS:
+        c = g.integers(lo, hi + 1, size=(3, 2))
+        a, p, q = (tuple(r) for r in c)
+        if a == p or a == q or p == q:
+            continue
+        out[t] = c
+        t += 1
+    return out
+
+
+def gaussian_weights(patch=8, sigma=2.0, peak=128):
+    """Integer weights[patch][patch]: peak * exp(-r^2 / (2 sigma^2)) rounded,
+    r the distance from the patch centre ((patch - 1) / 2 in each axis)."""
+    c = (patch - 1) / 2.0
+    i = np.arange(patch, dtype=np.float64) - c
+    r2 = i[:, None] ** 2 + i[None, :] ** 2
+    return np.rint(peak * np.exp(-r2 / (2.0 * sigma * sigma))).astype(np.uint8)
+
+
+def clatch_7x7_weights():
+    """8 x 8 weights emulating the 7 x 7 patch (Sec. 3.2): zero on the first
+    row and the first column, one elsewhere."""
+    w = np.ones((8, 8), np.uint8)
+    w[0, :] = 0
+    w[:, 0] = 0
+    return w
+
+
 def smoothed_noise(g, height, width, sigma=1.5, mean=128.0, std=48.0):
     """i.i.d. U{0..255}, Gaussian sigma (radius 5, reflect), stretched to mean/std."""
     raw = g.integers(0, 256, size=(height, width)).astype(np.float64)
