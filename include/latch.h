@@ -108,6 +108,29 @@ typedef struct {
  */
 int latch_create(latch_handle *h, const uint8_t *triplets_host);
 
+/*
+ * Create a handle whose extraction uses another window and patch geometry and
+ * per-pixel integer patch weights (Sec. 3.2: the paper's CLATCH extracts from
+ * 64 x 64 windows with 8 x 8 patches, each patch pixel optionally weighted;
+ * zero weights on one row and column reproduce the 7 x 7 patch, and Gaussian
+ * weights are suggested).  Bit t is [S_1 > S_2] with
+ *     S_j = sum_{a,b < patch} w[a][b] (A[a][b] - P_j[a][b])^2,
+ * where the patch of centre (r, c) has its top-left pixel at
+ * (r - patch/2, c - patch/2), and window pixel (i, j) is sampled at offset
+ * (j - window/2, i - window/2) by the same resampling rule.
+ *   window:       48 or 64; patch: 7 or 8 (LATCH_ERANGE otherwise).
+ *   triplets_host: uint8[512][3][2] centres as for latch_create, each with its
+ *                 patch inside the window: r - patch/2 >= 0 and
+ *                 r - patch/2 + patch <= window (LATCH_ERANGE otherwise).
+ *   weights_host: uint8[patch][patch] row-major, each in [0, 128]
+ *                 (LATCH_ERANGE otherwise), or NULL for all ones.  Copied.
+ * 48 / 7 / all ones is the latch_create handle.  Any other geometry runs a
+ * second extraction kernel (16-bit packed arithmetic, exact), for
+ * latch_extract, latch_extract_batch and plans alike; matching is unchanged.
+ */
+int latch_create_geometry(latch_handle *h, const uint8_t *triplets_host, int window, int patch,
+                          const uint8_t *weights_host);
+
 /* Release a handle and its device memory (synchronises the device first).  NULL is a no-op. */
 void latch_destroy(latch_handle h);
 

@@ -31,7 +31,7 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
                 -4: "LATCH_ERANGE"}
 
 # Every symbol include/latch.h declares.
-EXPORTS = ("latch_create", "latch_destroy", "latch_extract", "latch_extract_batch", "latch_detect",
+EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "latch_extract", "latch_extract_batch", "latch_detect",
            "hamming_knn",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
            "latch_get_tuning", "latch_set_tuning",
@@ -67,6 +67,8 @@ def load_library():
     P, I, I64, F = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_float
     lib.latch_create.argtypes = [ctypes.POINTER(P), P]
     lib.latch_create.restype = I
+    lib.latch_create_geometry.argtypes = [ctypes.POINTER(P), P, I, I, P]
+    lib.latch_create_geometry.restype = I
     lib.latch_destroy.argtypes = [P]
     lib.latch_destroy.restype = None
     lib.latch_extract.argtypes = [P, P, I, I, I, P, I64, P, P]
@@ -151,6 +153,22 @@ def latch_create(triplets):
     rc = load_library().latch_create(ctypes.byref(h), trip.ctypes.data_as(ctypes.c_void_p))
     if rc != LATCH_OK:
         raise LatchError(rc, "latch_create failed")
+    return h
+
+
+def latch_create_geometry(triplets, window=64, patch=8, weights=None):
+    """Create a handle with window side `window` (48, 64), patch side `patch`
+    (7, 8) and integer weights uint8[patch, patch] in [0, 128] (None: ones)."""
+    trip = np.ascontiguousarray(np.asarray(triplets, np.uint8).reshape(512, 3, 2))
+    wp = None
+    if weights is not None:
+        w = np.ascontiguousarray(np.asarray(weights, np.uint8).reshape(patch, patch))
+        wp = w.ctypes.data_as(ctypes.c_void_p)
+    h = ctypes.c_void_p()
+    rc = load_library().latch_create_geometry(ctypes.byref(h), trip.ctypes.data_as(ctypes.c_void_p),
+                                              int(window), int(patch), wp)
+    if rc != LATCH_OK:
+        raise LatchError(rc, "latch_create_geometry failed")
     return h
 
 
@@ -414,8 +432,14 @@ def latch_timing_read(h, kernel):
 class Latch:
     """Owning wrapper of a handle (the same calls, with the handle bound)."""
 
-    def __init__(self, triplets):
-        self.h = latch_create(triplets)
+    def __init__(self, triplets, window=None, patch=None, weights=None):
+        """The default geometry (48 x 48 window, 7 x 7 patches, unit weights),
+        or another one (latch_create_geometry) when any of window, patch or
+        weights is given."""
+        if window is None and patch is None and weights is None:
+            self.h = latch_create(triplets)
+        else:
+            self.h = latch_create_geometry(triplets, window or 48, patch or 7, weights)
 
     def extract(self, img, kps, desc=None, stream=None):
         return latch_extract(self.h, img, kps, desc, stream)

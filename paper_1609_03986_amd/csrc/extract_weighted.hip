@@ -1,0 +1,202 @@
+// LATCH extraction with the paper's CLATCH geometry and per-pixel patch
+// weights (Sec. 3.2: 64 x 64 windows, 8 x 8 patches, an integer weight per
+// patch pixel; zero weights on one row and one column give the 7 x 7 patch).
+//
+// For each triplet, S_j = sum w[a][b] (A[a][b] - P_j[a][b])^2 over the patch
+// pixels and bit = [S_1 > S_2].  Weights lie in [0, 128], so w d fits a signed
+// 16-bit lane for every pixel difference d in [-255, 255]: per patch row of 8
+// pixels (4 pairs) the kernel forms d with v_pk_sub_i16, w d with
+// v_pk_mul_lo_u16 and accumulates d (w d) with v_dot2_i32_i16.  Every sum is
+// below 64 * 128 * 255^2 < 2^31: exact.  7 x 7 patches run as 8 x 8 ones
+// whose last row and column weigh 0.
+//
+// A workgroup of four wavefronts computes one descriptor at a time
+// (grid-stride over keypoints):
+//   1. resampling rule steps 1-3 on the keypoint (uniform);
+//   2. the W x W window gathered with the rule (W * W / 256 samples per
+//      thread, issued one keypoint ahead), written to LDS as 16-bit pixels
+//      in four copies shifted by 0..3 columns, so that the 8 pixels of any
+//      patch row start on a quadword of one copy (one ds_read2_b64);
+//   3. two triplets per thread; one ballot per wavefront and triplet set
+//      gives 64 bits.
+#include "internal.h"
+
+namespace latch {
+namespace {
+
+#include "keypoint.h"
+
+typedef short short2v __attribute__((ext_vector_type(2)));
+
+constexpr int kWThreads = 256;
+
+template <int kW>
+struct WGeom {
+    static constexpr int kHalfW = kW / 2;
+    static constexpr int kRowBytes = 2 * (kW + 8);               // 16-bit pixels, 8 spare
+    static constexpr int kCopyBytes = (kW + 1) * kRowBytes;      // one spare (zero) row
+    static constexpr int kLds = 4 * kCopyBytes;
+    static constexpr int kSamples = kW * kW / kWThreads;         // per thread
+    static_assert(kW * kW % kWThreads == 0, "whole samples per thread");
+};
+
+// Rule steps 4-5 for window position q = i W + j (u = j - W/2, v = i - W/2).
+template <int kW>
+__device__ __forceinline__ uint32_t sample(const Keypoint &k, GlobalByte *img, int q)
+{
+    const int u = (q % kW) - WGeom<kW>::kHalfW, v = (q / kW) - WGeom<kW>::kHalfW;
+    const int ox = round_q22(mul_i24(mad_i24(k.c, u, mul_i24(-k.s, v)), k.sq));
+    const int oy = round_q22(mul_i24(mad_i24(k.s, u, mul_i24(k.c, v)), k.sq));
+    if (k.interior) return img[(uint32_t)(k.cy * k.pitch + k.cx + mad_i24(oy, k.pitch, ox))];
+    const int x = clamp_med3(k.cx + ox, 0, k.width - 1);
+    const int y = clamp_med3(k.cy + oy, 0, k.height - 1);
+    return img[(uint32_t)mad_i24(y, k.pitch, x)];
+}
+
+template <int kW>
+__device__ __forceinline__ void issue_samples(const Keypoint &k, int tid,
+                                              uint32_t (&g)[WGeom<kW>::kSamples])
+{
+    GlobalByte *img = (GlobalByte *)k.img;
+#pragma unroll
+    for (int m = 0; m < WGeom<kW>::kSamples; ++m) g[m] = sample<kW>(k, img, tid + kWThreads * m);
+}
+
+// Pixel (i, j) goes to element j - s of row i of copy s, s = 0..3 (j >= s).
+template <int kW>
+__device__ __forceinline__ void write_window(uint8_t *lds, int tid, const uint32_t (&g)[WGeom<kW>::kSamples])
+{
+    using G = WGeom<kW>;
+#pragma unroll
+    for (int m = 0; m < G::kSamples; ++m) {
+        const int q = tid + kWThreads * m;
+        const int i = q / kW, j = q % kW;
+        uint8_t *row = lds + i * G::kRowBytes + 2 * j;
+        const uint16_t v = (uint16_t)g[m];
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+            if (j >= s) *reinterpret_cast<uint16_t *>(row + s * G::kCopyBytes - 2 * s) = v;
+    }
+}
+
+// S_j of one triplet: patch rows at byte offsets off + r kRowBytes.
+template <int kW>
+__device__ __forceinline__ bool weighted_bit(const uint8_t *lds, uint32_t oa, uint32_t o1, uint32_t o2,
+                                             const WeightRows &w)
+{
+    using G = WGeom<kW>;
+    int s1 = 0, s2 = 0;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) {
+        // Patch rows start on quadwords (not 16-byte lines): two 8-byte reads.
+        const uint2 *pa = reinterpret_cast<const uint2 *>(lds + oa + r * G::kRowBytes);
+        const uint2 *pc = reinterpret_cast<const uint2 *>(lds + o1 + r * G::kRowBytes);
+        const uint2 *pe = reinterpret_cast<const uint2 *>(lds + o2 + r * G::kRowBytes);
+        const uint2 a0 = pa[0], a1 = pa[1], c0 = pc[0], c1 = pc[1], e0 = pe[0], e1 = pe[1];
+        const uint32_t av[4] = {a0.x, a0.y, a1.x, a1.y}, cv[4] = {c0.x, c0.y, c1.x, c1.y},
+                       ev[4] = {e0.x, e0.y, e1.x, e1.y};
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const short2v wv = __builtin_bit_cast(short2v, w.pair[4 * r + i]);
+            const short2v A = __builtin_bit_cast(short2v, av[i]);
+            const short2v d1 = A - __builtin_bit_cast(short2v, cv[i]);
+            const short2v d2 = A - __builtin_bit_cast(short2v, ev[i]);
+            s1 = __builtin_amdgcn_sdot2(wv * d1, d1, s1, false);
+            s2 = __builtin_amdgcn_sdot2(wv * d2, d2, s2, false);
+        }
+    }
+    return s1 > s2;
+}
+
+template <bool kTable, int kW>
+__global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
+    ImageSource src, const float4 *__restrict__ kps, int64_t n_host, const int64_t *__restrict__ n_dev,
+    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off, WeightRows w,
+    uint32_t *__restrict__ desc, uint32_t *__restrict__ flags)
+{
+    using G = WGeom<kW>;
+    __shared__ __attribute__((aligned(16))) uint8_t lds[G::kLds];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+
+    // The spare columns and row stay zero (they meet zero weights only).
+    for (int i = tid; i < G::kLds / 4; i += kWThreads) reinterpret_cast<uint32_t *>(lds)[i] = 0u;
+
+    // Triplets tid and 256 + tid: bits 64 wave + lane of words 0..7 and 8..15.
+    const uint2 t0 = trip_off[tid], t1 = trip_off[kWThreads + tid];
+
+    int64_t n = n_host;
+    if (n_dev) n = min(n, *n_dev);
+    int64_t p = blockIdx.x;
+    if (p >= n) return;
+    const int64_t stride = gridDim.x;
+    uint32_t g[G::kSamples];
+    KeypointBatch batch = prepare_batch<kTable, G::kHalfW>(kps, n, p, stride, lane, rot, src);
+    bool bad_image = false;
+    Keypoint cur = batch_get<kTable>(batch, 0, src, &bad_image);
+    if (cur.ok) issue_samples<kW>(cur, tid, g);
+
+    for (int i = 0; p < n; ++i, p += stride) {
+        const bool compute = cur.ok;
+        __syncthreads();   // the previous descriptor's patch reads are done
+        if (!compute) {
+            if (tid < kWords) uniform_words(desc + p * kWords)[(uint32_t)tid] = 0u;
+            if (tid == 0) atomicOr(flags, bad_image ? kFlagBadImage : kFlagBadKeypoint);
+        } else {
+            write_window<kW>(lds, tid, g);
+        }
+        __syncthreads();   // window complete
+
+        // Next keypoint's gather, in flight during the arithmetic below.
+        const int j = (i + 1) & 63;
+        if (j == 0) batch = prepare_batch<kTable, G::kHalfW>(kps, n, p + stride, stride, lane, rot, src);
+        cur = batch_get<kTable>(batch, j, src, &bad_image);
+        if (cur.ok) issue_samples<kW>(cur, tid, g);
+        if (!compute) continue;
+
+        const uint64_t b0 = __ballot(weighted_bit<kW>(lds, t0.x & 0xffffu, t0.x >> 16, t0.y, w));
+        const uint64_t b1 = __ballot(weighted_bit<kW>(lds, t1.x & 0xffffu, t1.x >> 16, t1.y, w));
+        if (lane < 4) {
+            const uint64_t b = lane < 2 ? b0 : b1;
+            const uint32_t word = (uint32_t)(lane & 1 ? b >> 32 : b);
+            desc[p * kWords + 8 * (lane >> 1) + 2 * wave + (lane & 1)] = word;
+        }
+    }
+}
+
+template <int kW>
+hipError_t launch_weighted_w(const ExtractArgs &a, hipStream_t stream)
+{
+    int64_t blocks = a.n;
+    const int64_t resident = (int64_t)a.num_cus * (kLdsPerCu / WGeom<kW>::kLds);
+    if (blocks > resident) blocks = resident;
+    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
+    if (a.table)
+        hipLaunchKernelGGL((extract_weighted_kernel<true, kW>), dim3((unsigned)blocks), dim3(kWThreads),
+                           0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off, a.weights,
+                           a.desc, a.flags);
+    else
+        hipLaunchKernelGGL((extract_weighted_kernel<false, kW>), dim3((unsigned)blocks),
+                           dim3(kWThreads), 0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off,
+                           a.weights, a.desc, a.flags);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+uint32_t weighted_patch_offset(int window, int top, int left)
+{
+    const int s = left & 3, e = left - s;
+    if (window == 64)
+        return (uint32_t)(s * WGeom<64>::kCopyBytes + top * WGeom<64>::kRowBytes + 2 * e);
+    return (uint32_t)(s * WGeom<48>::kCopyBytes + top * WGeom<48>::kRowBytes + 2 * e);
+}
+
+hipError_t launch_extract_weighted(const ExtractArgs &a, hipStream_t stream)
+{
+    if (a.n <= 0) return hipSuccess;
+    return a.window == 64 ? launch_weighted_w<64>(a, stream) : launch_weighted_w<48>(a, stream);
+}
+
+}  // namespace latch

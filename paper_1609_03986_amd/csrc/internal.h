@@ -58,6 +58,12 @@ struct ImageEntry {
 };
 static_assert(sizeof(ImageEntry) == 24, "latch_image layout");
 
+// Per-pixel patch weights of the weighted kernel: row r, pixel pair i of an
+// 8 x 8 patch as two 16-bit lanes (w[r][2i] | w[r][2i + 1] << 16).
+struct WeightRows {
+    uint32_t pair[32];
+};
+
 struct ExtractArgs {
     const uint8_t *img;            // single image (table == nullptr)
     int height, width, pitch;
@@ -73,9 +79,17 @@ struct ExtractArgs {
     uint32_t *desc;
     uint32_t *flags;
     int num_cus;
+    // Weighted geometry (window 0: the default 48 x 48, 7 x 7, unit weights).
+    int window = 0;
+    const uint2 *wtrip_off = nullptr;   // [512] in triplet order: LDS byte offsets of the patches
+    WeightRows weights = {};
 };
 
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
+hipError_t launch_extract_weighted(const ExtractArgs &a, hipStream_t stream);
+// LDS byte offset of the top-left pixel (top, left) of a patch in the
+// weighted kernel's window of side `window` (48 or 64).
+uint32_t weighted_patch_offset(int window, int top, int left);
 
 // Keypoint detection (FAST-9, suppression, intensity-centroid orientation).
 constexpr int kDetectBorder = 16;

@@ -1,0 +1,173 @@
+// Device helpers shared by the extraction kernels: resampling rule steps 1-3
+// for batches of keypoints (with the image each keypoint samples), and the
+// exact small-integer arithmetic of rule step 4.  Included inside
+// namespace latch { namespace { ... } } of each kernel file.
+#pragma once
+
+typedef const __attribute__((address_space(1))) uint8_t GlobalByte;
+typedef __attribute__((address_space(1))) uint32_t GlobalWord;
+
+// A wavefront-uniform global pointer, kept in scalar registers.
+__device__ __forceinline__ GlobalWord *uniform_words(uint32_t *ptr)
+{
+    const uint64_t v = reinterpret_cast<uintptr_t>(ptr);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+    return (GlobalWord *)(lo | (hi << 32));
+}
+
+// n / 2^22 rounded half away from zero, for |n| < 2^31 - 2^21.
+// n >= 0: floor((n + 2^21) / 2^22).  n < 0: floor((n + 2^21 - 1) / 2^22),
+// which equals ceil((n - 2^21) / 2^22) = -floor((-n + 2^21) / 2^22).
+__device__ __forceinline__ int round_q22(int n)
+{
+    return (n + (1 << 21) + (n >> 31)) >> 22;
+}
+
+__device__ __forceinline__ int clamp_med3(int x, int lo, int hi)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// 24-bit signed multiplies, kept as such (the compiler would otherwise fold
+// them into quarter-rate 32-bit multiplies by the precomputed sq * C).
+__device__ __forceinline__ int mul_i24(int a, int b)
+{
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ int mad_i24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc)
+{
+    return __builtin_amdgcn_udot4(a, b, acc, false);
+}
+
+// Rule steps 1-3 for one keypoint (uniform across the workgroup), with the
+// image it samples.
+struct Keypoint {
+    bool ok;        // inside the rule's domain (and a real keypoint)
+    bool interior;  // every sample lies inside the image: no clamping needed
+    int cx, cy;
+    int c, s, sq;   // C[b], S[b] (Q14) and the Q8 scale
+    const uint8_t *img;
+    int height, width, pitch;
+};
+
+// Where keypoints find their image: one image given by value, or a device
+// table of images indexed by a per-keypoint image id.
+struct ImageSource {
+    const uint8_t *img;          // single image
+    int height, width, pitch;
+    const ImageEntry *table;     // batch: table[image_id[k]]
+    const int32_t *image_id;
+    int n_images;
+};
+
+// Rule steps 1-3 for 64 keypoints at once: lane j takes keypoint
+// first + j * stride.  The result stays in registers; each keypoint's
+// parameters are then read out with readlane, so the two dependent loads
+// (record, table entry) are paid once per 64 keypoints.
+struct KeypointBatch {
+    int cx, cy;
+    int cs;          // C[b] & 0xffff | S[b] << 16
+    int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18
+    int id;          // image table: the keypoint's image (0 when out of range)
+};
+
+// kHalfSide: the largest |u|, |v| of a window position (half the window side).
+template <bool kTable, int kHalfSide>
+__device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict__ kps, int64_t n,
+                                                       int64_t first, int64_t stride, int lane,
+                                                       const int2 *__restrict__ rot,
+                                                       const ImageSource &src)
+{
+    KeypointBatch kb;
+    const int64_t idx = first + stride * lane;
+    const bool real = idx < n;
+    const uint8_t *img = src.img;
+    int height = src.height, width = src.width, pitch = src.pitch;
+    bool image_ok = true;
+    int image_id = 0;
+    if (kTable) {
+        const int id = real ? src.image_id[idx] : 0;
+        image_ok = id >= 0 && id < src.n_images;
+        image_id = image_ok ? id : 0;
+        const ImageEntry e = image_ok ? src.table[id] : ImageEntry{nullptr, 1, 1, 1, 0};
+        img = e.img;
+        height = e.height;
+        width = e.width;
+        pitch = e.pitch;
+        image_ok = image_ok && img != nullptr && height >= 1 && width >= 1 && pitch >= width &&
+                   height < (1 << 23) && pitch < (1 << 23) &&
+                   (int64_t)height * pitch <= (int64_t)0x7fffffff;
+        if (!image_ok) {
+            height = width = pitch = 1;
+        }
+    }
+    const float4 kp = real ? kps[idx] : make_float4(0.f, 0.f, 0.f, 0.f);
+    bool ok = real && image_ok && __builtin_isfinite(kp.x) && __builtin_isfinite(kp.y) &&
+              __builtin_isfinite(kp.z) && __builtin_isfinite(kp.w);
+    ok = ok && fabsf(kp.x) <= 16777216.0f && fabsf(kp.y) <= 16777216.0f && fabsf(kp.z) <= 1.0e6f;
+    const double sqd = ok ? rint((double)kp.w * 256.0) : 0.0;
+    ok = ok && sqd >= 1.0 && sqd <= 1024.0;
+    int cx = 0, cy = 0, bin = 0, sq = 0;
+    if (ok) {
+        cx = (int)floor((double)kp.x + 0.5);
+        cy = (int)floor((double)kp.y + 0.5);
+        bin = (int)rint((double)kp.z * (4096.0 / 360.0)) & (kBins - 1);
+        sq = (int)sqd;
+    }
+    const int2 cs = rot[bin];
+    // |offset| <= (kHalfSide sq (|C| + |S|) + 2^21) / 2^22 < reach.
+    const int reach = ((kHalfSide * sq * (abs(cs.x) + abs(cs.y))) >> 22) + 1;
+    const bool interior = ok && cx - reach >= 0 && cx + reach <= width - 1 && cy - reach >= 0 &&
+                          cy + reach <= height - 1;
+    kb.cx = cx;
+    kb.cy = cy;
+    kb.cs = (cs.x & 0xffff) | (cs.y << 16);
+    kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18);
+    kb.id = image_id;
+    return kb;
+}
+
+template <bool kTable>
+__device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, const ImageSource &src,
+                                              bool *bad_image)
+{
+    Keypoint k;
+    k.cx = __builtin_amdgcn_readlane(kb.cx, j);
+    k.cy = __builtin_amdgcn_readlane(kb.cy, j);
+    const int cs = __builtin_amdgcn_readlane(kb.cs, j);
+    const int f = __builtin_amdgcn_readlane(kb.sq_flags, j);
+    k.c = (int)(short)(cs & 0xffff);
+    k.s = cs >> 16;
+    k.sq = f & 0xffff;
+    k.ok = (f >> 16) & 1;
+    k.interior = (f >> 17) & 1;
+    *bad_image = (f >> 18) & 1;
+    if (kTable) {
+        // The keypoint's image entry, a uniform (scalar) load; the entry was
+        // validated per lane in prepare_batch, and ok is false otherwise.
+        const ImageEntry e = src.table[__builtin_amdgcn_readlane(kb.id, j)];
+        k.img = e.img;
+        k.height = e.height;
+        k.width = e.width;
+        k.pitch = e.pitch;
+    } else {
+        k.img = src.img;
+        k.height = src.height;
+        k.width = src.width;
+        k.pitch = src.pitch;
+    }
+    return k;
+}

@@ -19,6 +19,10 @@ struct latch_ctx {
     uint2 *trip_off_dev = nullptr;     // [512] by slot: LDS byte offsets of the three patches
     uint32_t *unperm_dev = nullptr;    // [128] output-bit slots per (wavefront, lane)
     uint32_t *flags_dev = nullptr;     // sticky error word
+    // Weighted geometry (latch_create_geometry); window 0 runs the default kernel.
+    int window = 0;
+    uint2 *wtrip_dev = nullptr;        // [512] in triplet order: weighted-kernel patch offsets
+    WeightRows weights = {};
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
     latch_tuning tuning;               // LATCH_PATH_AUTO table and split targets
@@ -334,7 +338,44 @@ ExtractArgs batch_extract_args(latch_handle h, const latch_image *images_dev, in
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
+    a.window = h->window;
+    a.wtrip_off = h->wtrip_dev;
+    a.weights = h->weights;
     return a;
+}
+
+// The handle's extraction kernel: the weighted one for a geometry handle.
+hipError_t run_extract(const ExtractArgs &a, hipStream_t stream)
+{
+    return a.window ? launch_extract_weighted(a, stream) : launch_extract(a, stream);
+}
+
+// A handle with the rotation table and the error word (no triplet data).
+int create_base(latch_ctx **out)
+{
+    latch_ctx *h = new latch_ctx();
+    default_tuning(&h->tuning);
+    hipError_t e = hipGetDevice(&h->device);
+    if (e == hipSuccess)
+        e = hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e != hipSuccess || h->num_cus < 1) {
+        delete h;
+        return LATCH_EDEVICE;
+    }
+    int16_t c[kBins], s[kBins];
+    rotation_table(c, s);
+    int2 rot[kBins];
+    for (int a = 0; a < kBins; ++a) rot[a] = make_int2(c[a], s[a]);
+    if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipMemcpy(h->rot_dev, rot, sizeof rot, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(h->flags_dev, 0, sizeof(uint32_t))) != hipSuccess) {
+        const int rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
+        latch_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return LATCH_OK;
 }
 
 }  // namespace
@@ -364,19 +405,9 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
     for (int i = 0; i < kTriplets * 6; ++i)
         if (triplets_host[i] < kPatchR || triplets_host[i] > kWin - 1 - kPatchR) return LATCH_ERANGE;
 
-    latch_ctx *h = new latch_ctx();
-    default_tuning(&h->tuning);
-    hipError_t e = hipGetDevice(&h->device);
-    if (e == hipSuccess)
-        e = hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device);
-    if (e != hipSuccess || h->num_cus < 1) {
-        delete h;
-        return LATCH_EDEVICE;
-    }
-    int16_t c[kBins], s[kBins];
-    rotation_table(c, s);
-    int2 rot[kBins];
-    for (int a = 0; a < kBins; ++a) rot[a] = make_int2(c[a], s[a]);
+    latch_ctx *h = nullptr;
+    int rc = create_base(&h);
+    if (rc != LATCH_OK) return rc;
     uint2 toff[kTriplets];
     for (int t = 0; t < kTriplets; ++t) {
         const uint8_t *tr = triplets_host + 6 * t;
@@ -395,15 +426,62 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
         const int k = (t >> 6) & 3, l = t & 63;
         unperm[64 * w + l] |= (uint32_t)slot_of[t] << (8 * k);
     }
-    int rc = LATCH_OK;
-    if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) != hipSuccess ||
+    hipError_t e;
+    if ((e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) != hipSuccess ||
         (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMemcpy(h->rot_dev, rot, sizeof rot, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->trip_off_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->unperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemset(h->flags_dev, 0, sizeof(uint32_t))) != hipSuccess ||
+        (e = hipDeviceSynchronize()) != hipSuccess) {
+        rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
+        latch_destroy(h);
+        return rc;
+    }
+    *out = h;
+    return LATCH_OK;
+}
+
+int latch_create_geometry(latch_handle *out, const uint8_t *triplets_host, int window, int patch,
+                          const uint8_t *weights_host)
+{
+    if (!out || !triplets_host) return LATCH_EINVAL;
+    *out = nullptr;
+    if ((window != 48 && window != 64) || (patch != 7 && patch != 8)) return LATCH_ERANGE;
+    uint8_t w[64];
+    bool unit = true;
+    for (int i = 0; i < patch * patch; ++i) {
+        w[i] = weights_host ? weights_host[i] : 1;
+        if (w[i] > 128) return LATCH_ERANGE;
+        unit = unit && w[i] == 1;
+    }
+    for (int i = 0; i < kTriplets * 6; ++i) {
+        const int first = triplets_host[i] - patch / 2;
+        if (first < 0 || first + patch > window) return LATCH_ERANGE;
+    }
+    if (window == kWin && patch == 2 * kPatchR + 1 && unit) return latch_create(out, triplets_host);
+
+    latch_ctx *h = nullptr;
+    int rc = create_base(&h);
+    if (rc != LATCH_OK) return rc;
+    h->window = window;
+    // 7 x 7 patches run as 8 x 8 ones whose last row and column weigh 0.
+    for (int r = 0; r < 8; ++r)
+        for (int i = 0; i < 4; ++i) {
+            const int c0 = 2 * i, c1 = 2 * i + 1;
+            const uint32_t lo = (r < patch && c0 < patch) ? w[r * patch + c0] : 0u;
+            const uint32_t hi = (r < patch && c1 < patch) ? w[r * patch + c1] : 0u;
+            h->weights.pair[4 * r + i] = lo | (hi << 16);
+        }
+    uint2 toff[kTriplets];
+    for (int t = 0; t < kTriplets; ++t) {
+        const uint8_t *tr = triplets_host + 6 * t;
+        uint32_t o[3];
+        for (int k = 0; k < 3; ++k)
+            o[k] = weighted_patch_offset(window, tr[2 * k] - patch / 2, tr[2 * k + 1] - patch / 2);
+        toff[t] = make_uint2(o[0] | (o[1] << 16), o[2]);
+    }
+    hipError_t e;
+    if ((e = hipMalloc((void **)&h->wtrip_dev, sizeof toff)) != hipSuccess ||
+        (e = hipMemcpy(h->wtrip_dev, toff, sizeof toff, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
         latch_destroy(h);
@@ -421,6 +499,7 @@ void latch_destroy(latch_handle h)
     if (h->trip_off_dev) (void)hipFree(h->trip_off_dev);
     if (h->unperm_dev) (void)hipFree(h->unperm_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
+    if (h->wtrip_dev) (void)hipFree(h->wtrip_dev);
     if (h->ws) (void)hipFree(h->ws);
     release_timed(h);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
@@ -461,7 +540,10 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
-    hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
+    a.window = h->window;
+    a.wtrip_off = h->wtrip_dev;
+    a.weights = h->weights;
+    hipError_t e = timed_launch(h, "extract", stream, [&] { return run_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
 }
 
@@ -479,7 +561,7 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
         return fail(h, LATCH_EINVAL, "null buffer or empty image table");
     const ExtractArgs a = batch_extract_args(h, images_dev, n_images, image_id_dev, kps_dev,
                                              max_kps, n_kps_dev, desc_dev);
-    hipError_t e = timed_launch(h, "extract", stream, [&] { return launch_extract(a, stream); });
+    hipError_t e = timed_launch(h, "extract", stream, [&] { return run_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
 }
 
@@ -692,7 +774,7 @@ int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
     hipStream_t s = nullptr;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess && d->max_kps > 0) e = launch_extract(ea, s);
+    if (e == hipSuccess && d->max_kps > 0) e = run_extract(ea, s);
     if (e == hipSuccess && d->n_pairs > 0) e = launch_knn_batch(ba, s);
     hipGraph_t graph = nullptr;
     if (s) {
