@@ -10,7 +10,7 @@ Inputs are resident in HBM before the timed region starts.
 Prints one JSON line.  `value` is descriptors extracted and matched per
 second for the whole step (20,000 descriptors per step).  Extra fields give
 the component rates (extraction desc/s, matching pairs/s per path,
-FAST detection of both images), step
+FAST detection of both images, the weighted 64 x 64 / 8 x 8 geometry), step
 latency percentiles, per-kernel durations from HIP events recorded by the
 library on its launch stream, the roofline of the dominant kernel and the
 CPU oracle baseline.
@@ -45,6 +45,11 @@ PEAK_DOT4_TOPS = CUS * LANES * CLOCK_GHZ * 8 / 1000.0   # 314.6
 EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 3                  # sub, mul, add per squared difference
 MATCH_OPS_PER_PAIR = 512 * 2                             # 512 MACs of a.b
 DETECT_THRESHOLD = 20                                    # FAST threshold of the detection component
+# Weighted CLATCH geometry: per descriptor 512 x 2 x 64 weighted squared
+# differences x 4 ops (sub, square, weight, add), against the chip's
+# v_dot2_i32_i16 rate (2 MACs = 4 ops per lane per cycle).
+WEIGHTED_OPS_PER_DESC = 512 * 2 * 64 * 4
+PEAK_DOT2_TOPS = CUS * LANES * CLOCK_GHZ * 4 / 1000.0   # 157.3
 
 
 def parse():
@@ -223,6 +228,31 @@ def main():
                               "peak": PEAK_HBM_GBS, "unit": "GB/s",
                               "frac": det_bytes / (det_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}}
 
+    # --- The paper's CLATCH geometry: the same 20,000 keypoints extracted
+    # from 64 x 64 windows with 8 x 8 patches and Gaussian integer weights
+    # (one batched launch of the weighted kernel). ---
+    geo_trip = synth.triplet_table_geom(64, 8)
+    geo = Latch(geo_trip, window=64, patch=8, weights=synth.gaussian_weights(8, 2.0, 128))
+    geo_desc = torch.empty_like(desc)
+
+    def extract_geometry():
+        geo.extract_batch(table, 2, image_id, kps, geo_desc)
+
+    g_wall, _ = timed_loop(extract_geometry, args.steps, 2)
+    geo.timing(True)
+    for _ in range(args.steps):
+        extract_geometry()
+    torch.cuda.synchronize()
+    n_g, g_total = geo.timing_read("extract")
+    geo.timing(False)
+    geo.close()
+    g_ms = g_total / max(n_g, 1)
+    g_ops = (nq + nt) * WEIGHTED_OPS_PER_DESC / (g_ms * 1e-3) / 1e12
+    weighted = {"geometry": "64x64 window, 8x8 patches, Gaussian weights (sigma 2, peak 128)",
+                "desc_per_s": (nq + nt) / (g_wall / args.steps), "avg_ms": g_ms,
+                "roofline": {"bound": "alu", "achieved": g_ops, "peak": PEAK_DOT2_TOPS,
+                             "unit": "TFLOP/s", "frac": g_ops / PEAK_DOT2_TOPS}}
+
     # --- The same step with the inputs starting in pinned host memory and the
     # results copied back (PCIe-inclusive; not the headline value). ---
     h_img_q = torch.from_numpy(w["query_image"]).pin_memory()
@@ -311,7 +341,8 @@ def main():
                        "pcie_inclusive_desc_per_s": pcie_desc_s,
                        "match_pairs_per_s": match_rates,
                        "match_kernel_avg_ms": match_kernel_ms,
-                       "detection": detection},
+                       "detection": detection,
+                       "weighted_extraction": weighted},
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,
