@@ -84,6 +84,8 @@ def _load():
         lib.oracle_triplets_valid_geom.restype = i32
         lib.oracle_extract_geom.argtypes = [P, i32, i32, i32, P, i64, P, i32, i32, P, P]
         lib.oracle_extract_geom.restype = ctypes.c_uint
+        lib.oracle_knn_window.argtypes = [P, P, i32, i32, i32, i32, ctypes.c_float, P, P, P]
+        lib.oracle_knn_window.restype = None
         _lib = lib
     return _lib
 
@@ -252,6 +254,38 @@ def extract_geom(img, kps, triplets, window=64, patch=8, weights=None):
     f = _load().oracle_extract_geom(_ptr(img), img.shape[0], img.shape[1], img.shape[1], _ptr(kps), n,
                                     _ptr(trip), int(window), int(patch), _ptr(w), _ptr(desc))
     return desc, int(f)
+
+
+def dense_keypoints(x0, y0, gw, gh):
+    """Keypoints (x, y, 0, 1) at every pixel of [x0, x0 + gw) x [y0, y0 + gh), raster order."""
+    ys, xs = np.mgrid[y0:y0 + gh, x0:x0 + gw]
+    kps = np.zeros((gh * gw, 4), np.float32)
+    kps[:, 0] = xs.reshape(-1)
+    kps[:, 1] = ys.reshape(-1)
+    kps[:, 3] = 1.0
+    return kps
+
+
+def extract_dense(img, x0, y0, gw, gh, triplets):
+    """Dense CLATCH (Sec. 6): the descriptor of every pixel of the region,
+    upright and at scale 1 -- by definition extraction at those keypoints.
+    Returns uint32 [gh * gw, 16] in raster order."""
+    desc, _ = extract(img, dense_keypoints(x0, y0, gw, gh), triplets)
+    return desc
+
+
+def knn_window(query, train, gw, gh, radius, k=2, ratio=0.8):
+    """Dense matching of two gh x gw descriptor grids: per query pixel the k
+    nearest train pixels within +/- radius rows and columns (raster indices)."""
+    q = np.ascontiguousarray(np.asarray(query, np.uint32).reshape(gh * gw, WORDS))
+    t = np.ascontiguousarray(np.asarray(train, np.uint32).reshape(gh * gw, WORDS))
+    n = gh * gw
+    idx = np.zeros((n, k), np.int32)
+    dist = np.zeros((n, k), np.int32)
+    acc = np.zeros(n, np.uint8)
+    _load().oracle_knn_window(_ptr(q), _ptr(t), int(gw), int(gh), int(radius), int(k), float(ratio),
+                              _ptr(idx), _ptr(dist), _ptr(acc))
+    return idx, dist, acc
 
 
 def hamming(a, b):

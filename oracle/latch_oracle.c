@@ -23,6 +23,8 @@
  *   - Sec. 3.2 "Weighing pixels in LATCH patches": the CLATCH geometry (64 x 64
  *     windows, 8 x 8 patches) with an integer weight per patch pixel
  *     (oracle_extract_geom).
+ *   - Sec. 6: dense per-pixel CLATCH and matching within a search window
+ *     (oracle_knn_window; dense extraction is extraction at every pixel).
  *   - Sec. 4 "Descriptor matching on the GPU": exhaustive (brute-force)
  *     Hamming matching.  k = 2 nearest neighbours, ties to the lowest train
  *     index, ratio test d1 < ratio * d2 evaluated exactly.
@@ -336,6 +338,53 @@ unsigned oracle_extract_geom(const uint8_t *img, int height, int width, int pitc
         free(tile);
     }
     return flags;
+}
+
+int oracle_hamming(const uint32_t *a, const uint32_t *b);
+
+/* ------------------------------------------------------------------------ */
+/* Dense matching (Sec. 6: CLATCH for dense pixel matching).                 */
+/* ------------------------------------------------------------------------ */
+/*
+ * query and train are descriptor grids of gh rows and gw columns (row-major,
+ * 16 words per pixel).  For query pixel (y, x) the candidates are the train
+ * pixels (y', x') with |y' - y| <= radius and |x' - x| <= radius inside the
+ * grid, scanned in raster order; the k = 1 or 2 nearest by Hamming distance,
+ * ties to the lower raster index y' gw + x', and the ratio test as in
+ * oracle_knn.  idx holds raster indices (-1 and distance 513 when missing).
+ */
+void oracle_knn_window(const uint32_t *query, const uint32_t *train, int gw, int gh, int radius,
+                       int k, float ratio, int32_t *idx, int32_t *dist, uint8_t *accept)
+{
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t q = 0; q < (int64_t)gw * gh; ++q) {
+        int y = (int)(q / gw), x = (int)(q % gw);
+        int b1 = -1, b2 = -1, d1 = OR_NO_NEIGHBOUR_DIST, d2 = OR_NO_NEIGHBOUR_DIST;
+        int n = 0;
+        for (int yy = y - radius; yy <= y + radius; ++yy) {
+            if (yy < 0 || yy >= gh) continue;
+            for (int xx = x - radius; xx <= x + radius; ++xx) {
+                if (xx < 0 || xx >= gw) continue;
+                int j = yy * gw + xx;
+                int d = oracle_hamming(query + OR_WORDS * q, train + OR_WORDS * (int64_t)j);
+                ++n;
+                if (d < d1) {
+                    b2 = b1; d2 = d1;
+                    b1 = j; d1 = d;
+                } else if (d < d2) {
+                    b2 = j; d2 = d;
+                }
+            }
+        }
+        idx[k * q] = b1;
+        dist[k * q] = d1;
+        if (k == 2) {
+            idx[k * q + 1] = b2;
+            dist[k * q + 1] = d2;
+        }
+        if (accept)
+            accept[q] = (uint8_t)(n >= 2 && (double)d1 < (double)ratio * (double)d2);
+    }
 }
 
 /* Hamming distance between two 512-bit descriptors. */
