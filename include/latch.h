@@ -172,6 +172,34 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
                         hipStream_t stream);
 
 /*
+ * Dense CLATCH (Sec. 6 proposes CLATCH for dense pixel matching): the
+ * descriptor of every pixel (x, y) of the region [x0, x0 + gw) x [y0, y0 + gh),
+ * upright and at scale 1 -- exactly latch_extract at the keypoints
+ * (x, y, 0, 1) -- computed with box filters over the region instead of per
+ * keypoint.  Needs a latch_create handle (LATCH_EINVAL for a geometry handle).
+ *   img_dev: as latch_extract.  The region may extend past the image (samples
+ *            clamp to the edge); |x0|, |y0|, x0 + gw, y0 + gh <= 2^24 and
+ *            gw * gh < 2^31 (LATCH_ERANGE otherwise).
+ *   desc_dev: uint32[gh][gw][16], raster order.
+ */
+int latch_extract_dense(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                        int x0, int y0, int gw, int gh, uint32_t *desc_dev, hipStream_t stream);
+
+/*
+ * Dense matching of two descriptor grids of gh rows and gw columns (Sec. 6):
+ * for query pixel (y, x), the k = 1 or 2 nearest train pixels by Hamming
+ * distance among (y', x') with |y' - y| <= radius, |x' - x| <= radius inside
+ * the grid; ties to the lower raster index; accept = at least two candidates
+ * and d1 < ratio * d2 (exact).  idx holds raster indices y' gw + x' (-1 and
+ * distance 513 when missing).
+ *   query_dev, train_dev: uint32[gh][gw][16]; radius in [0, 8] (LATCH_ERANGE).
+ *   idx_dev, dist_dev: int32[gh * gw][k]; accept_dev: uint8[gh * gw] or NULL.
+ */
+int hamming_knn_window(latch_handle h, const uint32_t *query_dev, const uint32_t *train_dev, int gw,
+                       int gh, int radius, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                       uint8_t *accept_dev, hipStream_t stream);
+
+/*
  * Keypoint detection (Sec. 3.2: the paper extracts LATCH at FAST keypoints
  * and their orientation; score, suppression and orientation method are
  * not stated there and are fixed as follows).
@@ -346,7 +374,7 @@ int latch_set_tuning(latch_handle h, const latch_tuning *t);
  * kernel the handle launches is bracketed by two hipEventRecord calls on the
  * launch stream.  latch_timing_enable(h, 1) starts a fresh record (0 stops
  * recording).  latch_timing_read waits for the recorded events and returns,
- * for one kernel name ("extract", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge",
+ * for one kernel name ("extract", "dense_extract", "knn_window", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge",
  * "knn_batch_mfma", "knn_batch_fp4", "knn_batch_popcount"; the batch names cover the whole
  * batched sequence), the number of launches recorded and their summed
  * duration in milliseconds.  Not for use under stream capture.

@@ -31,14 +31,15 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
                 -4: "LATCH_ERANGE"}
 
 # Every symbol include/latch.h declares.
-EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "latch_extract", "latch_extract_batch", "latch_detect",
+EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "latch_extract", "latch_extract_batch",
+           "latch_extract_dense", "hamming_knn_window", "latch_detect",
            "hamming_knn",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
            "latch_get_tuning", "latch_set_tuning",
            "latch_check_errors",
            "latch_last_error", "latch_rotation_table", "latch_version", "latch_timing_enable",
            "latch_timing_read")
-KERNELS = ("extract", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge", "knn_batch_mfma",
+KERNELS = ("extract", "dense_extract", "knn_window", "detect", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge", "knn_batch_mfma",
            "knn_batch_popcount")
 
 
@@ -75,6 +76,10 @@ def load_library():
     lib.latch_extract.restype = I
     lib.latch_extract_batch.argtypes = [P, P, I, P, P, I64, P, P, P]
     lib.latch_extract_batch.restype = I
+    lib.latch_extract_dense.argtypes = [P, P, I, I, I, I, I, I, I, P, P]
+    lib.latch_extract_dense.restype = I
+    lib.hamming_knn_window.argtypes = [P, P, P, I, I, I, I, F, P, P, P, P]
+    lib.hamming_knn_window.restype = I
     lib.latch_detect.argtypes = [P, P, I, I, I, I, P, I64, P, P, I, P]
     lib.latch_detect.restype = I
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
@@ -198,6 +203,40 @@ def latch_extract(h, img, kps, desc=None, stream=None):
                                       _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
     _check(h, rc)
     return desc
+
+
+def latch_extract_dense(h, img, x0, y0, gw, gh, desc=None, stream=None):
+    """Descriptors of every pixel of [x0, x0 + gw) x [y0, y0 + gh), upright at
+    scale 1: int32 [gh * gw, 16] (uint32 words), raster order."""
+    import torch
+    if img.dim() != 2:
+        raise ValueError("img must be 2-D")
+    if desc is None:
+        desc = torch.empty((gh * gw, 16), dtype=torch.int32, device=img.device)
+    H, W = img.shape
+    rc = load_library().latch_extract_dense(h, _dev(img, torch.uint8, "img"), H, W, img.stride(0),
+                                            int(x0), int(y0), int(gw), int(gh),
+                                            _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
+    _check(h, rc)
+    return desc
+
+
+def hamming_knn_window(h, query, train, gw, gh, radius, k=2, ratio=0.8, stream=None):
+    """Dense matching of two gh x gw descriptor grids within +/- radius:
+    (idx int32 [n, k] raster indices, dist int32 [n, k], accept uint8 [n])."""
+    import torch
+    n = gh * gw
+    dev = query.device
+    idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+    dist = torch.empty((n, k), dtype=torch.int32, device=dev)
+    acc = torch.empty((n,), dtype=torch.uint8, device=dev)
+    rc = load_library().hamming_knn_window(h, _dev(query, torch.int32, "query"),
+                                           _dev(train, torch.int32, "train"), int(gw), int(gh),
+                                           int(radius), int(k), float(ratio),
+                                           _dev(idx, torch.int32, "idx"), _dev(dist, torch.int32, "dist"),
+                                           _dev(acc, torch.uint8, "accept"), _stream_ptr(stream))
+    _check(h, rc)
+    return idx, dist, acc
 
 
 def latch_detect(h, img, threshold, max_kps, kps=None, n_kps=None, image_id=None, image_index=0,
@@ -443,6 +482,12 @@ class Latch:
 
     def extract(self, img, kps, desc=None, stream=None):
         return latch_extract(self.h, img, kps, desc, stream)
+
+    def extract_dense(self, img, x0, y0, gw, gh, desc=None, stream=None):
+        return latch_extract_dense(self.h, img, x0, y0, gw, gh, desc, stream)
+
+    def knn_window(self, query, train, gw, gh, radius, k=2, ratio=0.8, stream=None):
+        return hamming_knn_window(self.h, query, train, gw, gh, radius, k, ratio, stream)
 
     def detect(self, img, threshold, max_kps, **kw):
         return latch_detect(self.h, img, threshold, max_kps, **kw)

@@ -91,6 +91,31 @@ hipError_t launch_extract_weighted(const ExtractArgs &a, hipStream_t stream);
 // weighted kernel's window of side `window` (48 or 64).
 uint32_t weighted_patch_offset(int window, int top, int left);
 
+// Dense extraction (every pixel of a region, upright, scale 1) and dense
+// matching within a search window.
+struct DenseArgs {
+    const uint8_t *img;
+    int height, width, pitch;
+    int x0, y0, gw, gh;
+    const uint2 *toff;        // [512] triplet order: texture offsets of A | C1 << 16, C2
+    uint32_t *desc;
+};
+
+struct DenseMatchArgs {
+    const uint32_t *query, *train;
+    int gw, gh, radius, k;
+    float ratio;
+    int32_t *idx, *dist;
+    uint8_t *accept;
+};
+
+constexpr int kDenseMaxRadius = 8;
+
+hipError_t launch_dense_extract(const DenseArgs &a, hipStream_t stream);
+hipError_t launch_dense_match(const DenseMatchArgs &a, hipStream_t stream);
+// Texture offset of a patch centre (r, c) in the dense kernel's tile.
+uint32_t dense_patch_offset(int r, int c);
+
 // Keypoint detection (FAST-9, suppression, intensity-centroid orientation).
 constexpr int kDetectBorder = 16;
 constexpr int kOrientRadius = 15;

@@ -22,6 +22,7 @@ struct latch_ctx {
     // Weighted geometry (latch_create_geometry); window 0 runs the default kernel.
     int window = 0;
     uint2 *wtrip_dev = nullptr;        // [512] in triplet order: weighted-kernel patch offsets
+    uint2 *dense_off_dev = nullptr;    // [512] in triplet order: dense-kernel texture offsets
     WeightRows weights = {};
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
@@ -426,9 +427,17 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
         const int k = (t >> 6) & 3, l = t & 63;
         unperm[64 * w + l] |= (uint32_t)slot_of[t] << (8 * k);
     }
+    uint2 doff[kTriplets];
+    for (int t = 0; t < kTriplets; ++t) {
+        const uint8_t *tr = triplets_host + 6 * t;
+        doff[t] = make_uint2(dense_patch_offset(tr[0], tr[1]) | (dense_patch_offset(tr[2], tr[3]) << 16),
+                             dense_patch_offset(tr[4], tr[5]));
+    }
     hipError_t e;
     if ((e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) != hipSuccess ||
         (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->dense_off_dev, sizeof doff)) != hipSuccess ||
+        (e = hipMemcpy(h->dense_off_dev, doff, sizeof doff, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->trip_off_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(h->unperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
@@ -500,6 +509,7 @@ void latch_destroy(latch_handle h)
     if (h->unperm_dev) (void)hipFree(h->unperm_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
     if (h->wtrip_dev) (void)hipFree(h->wtrip_dev);
+    if (h->dense_off_dev) (void)hipFree(h->dense_off_dev);
     if (h->ws) (void)hipFree(h->ws);
     release_timed(h);
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
@@ -563,6 +573,68 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
                                              max_kps, n_kps_dev, desc_dev);
     hipError_t e = timed_launch(h, "extract", stream, [&] { return run_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
+}
+
+int latch_extract_dense(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
+                        int x0, int y0, int gw, int gh, uint32_t *desc_dev, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (!h->dense_off_dev)
+        return fail(h, LATCH_EINVAL, "dense extraction needs a handle of the default geometry");
+    if (height < 1 || width < 1 || pitch < width || height >= (1 << 23) || pitch >= (1 << 23) ||
+        (int64_t)height * pitch > (int64_t)INT32_MAX)
+        return fail(h, LATCH_EINVAL, "image %d x %d, pitch %d outside the limits", height, width, pitch);
+    if (gw < 0 || gh < 0 || (int64_t)gw * gh > LATCH_MAX_ROWS || x0 < -(1 << 24) || y0 < -(1 << 24) ||
+        (int64_t)x0 + gw > (1 << 24) || (int64_t)y0 + gh > (1 << 24))
+        return fail(h, LATCH_ERANGE, "region (%d, %d) + %d x %d outside the limits", x0, y0, gw, gh);
+    if (gw == 0 || gh == 0) return LATCH_OK;
+    if (!img_dev || !desc_dev) return fail(h, LATCH_EINVAL, "null buffer");
+    DenseArgs a;
+    a.img = img_dev;
+    a.height = height;
+    a.width = width;
+    a.pitch = pitch;
+    a.x0 = x0;
+    a.y0 = y0;
+    a.gw = gw;
+    a.gh = gh;
+    a.toff = h->dense_off_dev;
+    a.desc = desc_dev;
+    const hipError_t e =
+        timed_launch(h, "dense_extract", stream, [&] { return launch_dense_extract(a, stream); });
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "dense extract launch");
+}
+
+int hamming_knn_window(latch_handle h, const uint32_t *query_dev, const uint32_t *train_dev, int gw,
+                       int gh, int radius, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+                       uint8_t *accept_dev, hipStream_t stream)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (gw < 0 || gh < 0 || (int64_t)gw * gh > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "grid %d x %d", gw, gh);
+    if (radius < 0 || radius > kDenseMaxRadius)
+        return fail(h, LATCH_ERANGE, "radius %d (must be in [0, %d])", radius, kDenseMaxRadius);
+    if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
+    if (!(ratio > 0.0f && ratio <= 1.0f))
+        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
+    if (gw == 0 || gh == 0) return LATCH_OK;
+    if (!query_dev || !train_dev || !idx_dev || !dist_dev) return fail(h, LATCH_EINVAL, "null buffer");
+    DenseMatchArgs a;
+    a.query = query_dev;
+    a.train = train_dev;
+    a.gw = gw;
+    a.gh = gh;
+    a.radius = radius;
+    a.k = k;
+    a.ratio = ratio;
+    a.idx = idx_dev;
+    a.dist = dist_dev;
+    a.accept = accept_dev;
+    const hipError_t e =
+        timed_launch(h, "knn_window", stream, [&] { return launch_dense_match(a, stream); });
+    return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "dense match launch");
 }
 
 int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
