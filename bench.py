@@ -10,7 +10,8 @@ Inputs are resident in HBM before the timed region starts.
 Prints one JSON line.  `value` is descriptors extracted and matched per
 second for the whole step (20,000 descriptors per step).  Extra fields give
 the component rates (extraction desc/s, matching pairs/s per path,
-FAST detection of both images, the weighted 64 x 64 / 8 x 8 geometry), step
+FAST detection of both images, the weighted 64 x 64 / 8 x 8 geometry, dense
+per-pixel descriptors and windowed matching), step
 latency percentiles, per-kernel durations from HIP events recorded by the
 library on its launch stream, the roofline of the dominant kernel and the
 CPU oracle baseline.
@@ -50,6 +51,13 @@ DETECT_THRESHOLD = 20                                    # FAST threshold of the
 # v_dot2_i32_i16 rate (2 MACs = 4 ops per lane per cycle).
 WEIGHTED_OPS_PER_DESC = 512 * 2 * 64 * 4
 PEAK_DOT2_TOPS = CUS * LANES * CLOCK_GHZ * 4 / 1000.0   # 157.3
+# Dense CLATCH: per pixel and triplet, G = (C1 - C2)(C1 + C2 - 2A) (4 ops), a
+# running sum down the rows (2), one across the columns (2) and the compare
+# (1); dense matching: 32 ops per candidate (16 XOR + 16 popcount-add).  Both
+# against the 32-bit integer VALU rate (one op per lane per cycle).
+DENSE_OPS_PER_PIXEL = 512 * 9
+DENSE_RADIUS = 4
+PEAK_INT_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0         # 39.3
 
 
 def parse():
@@ -253,6 +261,41 @@ def main():
                 "roofline": {"bound": "alu", "achieved": g_ops, "peak": PEAK_DOT2_TOPS,
                              "unit": "TFLOP/s", "frac": g_ops / PEAK_DOT2_TOPS}}
 
+    # --- Dense CLATCH (Sec. 6): descriptors at every pixel of both images by
+    # box filters, then windowed 2-NN matching (radius DENSE_RADIUS). ---
+    H_img, W_img = img_q.shape
+    npx = H_img * W_img
+    dq = torch.empty((npx, 16), dtype=torch.int32, device=dev)
+    dt = torch.empty((npx, 16), dtype=torch.int32, device=dev)
+
+    def dense_both():
+        lat.extract_dense(img_q, 0, 0, W_img, H_img, dq)
+        lat.extract_dense(img_t, 0, 0, W_img, H_img, dt)
+
+    dense_steps = max(3, args.steps // 5)
+    de_wall, _ = timed_loop(dense_both, dense_steps, 1)
+    dm_wall, _ = timed_loop(lambda: lat.knn_window(dq, dt, W_img, H_img, DENSE_RADIUS), dense_steps, 1)
+    lat.timing(True)
+    for _ in range(dense_steps):
+        dense_both()
+        lat.knn_window(dq, dt, W_img, H_img, DENSE_RADIUS)
+    torch.cuda.synchronize()
+    n_de, t_de = lat.timing_read("dense_extract")
+    n_dm, t_dm = lat.timing_read("knn_window")
+    lat.timing(False)
+    de_ms, dm_ms = t_de / max(n_de, 1), t_dm / max(n_dm, 1)
+    de_ops = npx * DENSE_OPS_PER_PIXEL / (de_ms * 1e-3) / 1e12
+    cand = (2 * DENSE_RADIUS + 1) ** 2
+    dm_ops = npx * cand * 32 / (dm_ms * 1e-3) / 1e12
+    dense = {"image": "%dx%d, every pixel" % (W_img, H_img), "radius": DENSE_RADIUS,
+             "desc_per_s": 2 * npx / (de_wall / dense_steps), "extract_avg_ms": de_ms,
+             "match_pairs_per_s": npx * cand / (dm_wall / dense_steps), "match_avg_ms": dm_ms,
+             "extract_roofline": {"bound": "alu", "achieved": de_ops, "peak": PEAK_INT_TOPS,
+                                  "unit": "TFLOP/s", "frac": de_ops / PEAK_INT_TOPS},
+             "match_roofline": {"bound": "alu", "achieved": dm_ops, "peak": PEAK_INT_TOPS,
+                                "unit": "TFLOP/s", "frac": dm_ops / PEAK_INT_TOPS}}
+    del dq, dt
+
     # --- The same step with the inputs starting in pinned host memory and the
     # results copied back (PCIe-inclusive; not the headline value). ---
     h_img_q = torch.from_numpy(w["query_image"]).pin_memory()
@@ -342,7 +385,8 @@ def main():
                        "match_pairs_per_s": match_rates,
                        "match_kernel_avg_ms": match_kernel_ms,
                        "detection": detection,
-                       "weighted_extraction": weighted},
+                       "weighted_extraction": weighted,
+                       "dense": dense},
         "kernels": kernels,
         "roofline": roof,
         "cpu_baseline": cpu,

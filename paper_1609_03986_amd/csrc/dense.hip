@@ -40,13 +40,28 @@ __device__ __forceinline__ int mul24(int a, int b)
     return r;
 }
 
-// Sum of v over lanes l .. l + 6 (lanes past 63 contribute their own value;
-// only lanes 0 .. 57 are used).
+// 1 if h > 0, else 0, in one instruction (median of h, 0 and 1).
+__device__ __forceinline__ uint32_t bit_of(int h)
+{
+    int r;
+    asm("v_med3_i32 %0, %1, 0, 1" : "=v"(r) : "v"(h));
+    return (uint32_t)r;
+}
+
+// Lane l receives lane l + 1's value (DPP wave_shl:1; lane 63 receives 0
+// through bound_ctrl, so no old value has to be set up).
+__device__ __forceinline__ int lane_next(int v)
+{
+    return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
+}
+
+// Sum of v over lanes l .. l + 6 (only lanes 0 .. 57 are used), by a chain
+// of whole-wavefront DPP shifts: no LDS traffic and short latency.
 __device__ __forceinline__ int sum7_down(int v)
 {
-    const int s1 = v + __shfl_down(v, 1);
-    const int s2 = s1 + __shfl_down(s1, 2);          // v(l .. l + 3)
-    return s2 + __shfl_down(s1, 4) + __shfl_down(v, 6);
+    const int a1 = lane_next(v), a2 = lane_next(a1), a3 = lane_next(a2);
+    const int a4 = lane_next(a3), a5 = lane_next(a4), a6 = lane_next(a5);
+    return v + a1 + a2 + a3 + a4 + a5 + a6;
 }
 
 __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
@@ -60,19 +75,24 @@ __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
     const int lane = t & 63, wave = __builtin_amdgcn_readfirstlane(t >> 6);
 
     // Image rows Y0 - 24 .. Y0 + 54 and columns X0 - 24 .. X0 + 80, clamped
-    // to the image (the rule's clamp-to-edge), all loads before the stores.
-    uint32_t v[kDTexLoads];
+    // to the image (the rule's clamp-to-edge); three batches of 11 loads in
+    // flight, so that the staging does not set the kernel's register count.
+    static_assert(kDTexLoads == 33, "three batches of 11");
 #pragma unroll
-    for (int k = 0; k < kDTexLoads; ++k) {
-        const int i = t + k * kDThreads;
-        const int yy = min(max(Y0 - 24 + i / kDTexCols, 0), height - 1);
-        const int xx = min(max(X0 - 24 + i % kDTexCols, 0), width - 1);
-        v[k] = img[(size_t)yy * pitch + xx];
-    }
+    for (int batch = 0; batch < 3; ++batch) {
+        uint32_t v[11];
 #pragma unroll
-    for (int k = 0; k < kDTexLoads; ++k) {
-        const int i = t + k * kDThreads;
-        tex[(i / kDTexCols) * kDTexStride + i % kDTexCols] = (uint8_t)v[k];
+        for (int k = 0; k < 11; ++k) {
+            const int i = t + (11 * batch + k) * kDThreads;
+            const int yy = min(max(Y0 - 24 + i / kDTexCols, 0), height - 1);
+            const int xx = min(max(X0 - 24 + i % kDTexCols, 0), width - 1);
+            v[k] = img[(size_t)yy * pitch + xx];
+        }
+#pragma unroll
+        for (int k = 0; k < 11; ++k) {
+            const int i = t + (11 * batch + k) * kDThreads;
+            tex[(i / kDTexCols) * kDTexStride + i % kDTexCols] = (uint8_t)v[k];
+        }
     }
     __syncthreads();
 
@@ -96,11 +116,14 @@ __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
                 s += g;
                 if (rr >= 6) {
                     const int h = sum7_down(s);                // box over rows rr-6..rr, columns l..l+6
-                    bits[rr - 6] |= (uint32_t)(h > 0) << b;
+                    // Shift in from the right: triplet b ends at bit 31 - b.
+                    bits[rr - 6] = (bits[rr - 6] << 1) | bit_of(h);
                     s -= ring[(rr - 6) % 7];
                 }
             }
         }
+#pragma unroll
+        for (int o = 0; o < kDTileH; ++o) bits[o] = __builtin_bitreverse32(bits[o]);
         const int px = X0 + lane;
         if (lane < kDTileW && px < x0 + gw) {
 #pragma unroll
