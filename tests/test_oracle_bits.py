@@ -212,3 +212,55 @@ def test_golden_small_workload_descriptor_digest(triplets):
     assert f == 0
     assert hashlib.sha256(d.tobytes()).hexdigest() == g["sha256_first256"]
     assert hashlib.sha256(triplets.tobytes()).hexdigest() == g["sha256_triplets"]
+
+
+def test_float32_and_product_forms_agree_with_the_oracle(triplets):
+    """The paper computes in float32 (Sec. 3.2) and states CLATCH is identical to
+    LATCH: every partial sum is an integer below 49 * 255^2 < 2^24, so float32
+    accumulation is exact.  Three forms of Eq. 1 on whole tiles -- float32
+    sums of squared differences accumulated pixel by pixel, the int64 product
+    form S1 - S2 = sum (C1 - C2)(C1 + C2 - 2A), and the oracle -- give the
+    same 512 bits."""
+    g = np.random.default_rng(77)
+    trip = np.asarray(triplets).reshape(512, 3, 2).astype(np.int64)
+    for trial in range(6):
+        tile = (g.integers(0, 256, (48, 48)) if trial % 2 else
+                np.clip(g.normal(128, 60, (48, 48)), 0, 255)).astype(np.uint8)
+        want = oracle.describe_tile(tile, triplets)
+        f = tile.astype(np.float32)
+        t64 = tile.astype(np.int64)
+        got32 = np.zeros(16, np.uint32)
+        gotp = np.zeros(16, np.uint32)
+        for t in range(512):
+            (ra, ca), (r1, c1), (r2, c2) = trip[t]
+            s1 = np.float32(0)
+            s2 = np.float32(0)
+            for dr in range(-3, 4):
+                for dc in range(-3, 4):
+                    a = f[ra + dr, ca + dc]
+                    s1 = np.float32(s1 + (a - f[r1 + dr, c1 + dc]) ** 2)
+                    s2 = np.float32(s2 + (a - f[r2 + dr, c2 + dc]) ** 2)
+            A = t64[ra - 3:ra + 4, ca - 3:ca + 4]
+            P = t64[r1 - 3:r1 + 4, c1 - 3:c1 + 4]
+            Q = t64[r2 - 3:r2 + 4, c2 - 3:c2 + 4]
+            prod = int(((P - Q) * (P + Q - 2 * A)).sum())
+            if s1 > s2:
+                got32[t // 32] |= np.uint32(1 << (t % 32))
+            if prod > 0:
+                gotp[t // 32] |= np.uint32(1 << (t % 32))
+        assert np.array_equal(got32, want) and np.array_equal(gotp, want), trial
+
+
+def test_seeded_inputs_are_reproduced():
+    """The generators reproduce the stored SHA-256 of every workload array."""
+    import importlib.util
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+    spec = importlib.util.spec_from_file_location("make_input_digests", os.path.join(here, "make_input_digests.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    want = {}
+    for line in open(os.path.join(here, "input_digests.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = (x.strip() for x in line.split("="))
+            want[k] = v
+    assert mod.digests() == want
