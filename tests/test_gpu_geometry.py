@@ -129,3 +129,49 @@ def test_hd_sampled(torch_cuda):
         assert np.array_equal(got[sel], want)
     finally:
         lat.close()
+
+
+def test_plan_with_geometry_handle(torch_cuda):
+    """A captured plan (batched extraction + matching in one HIP graph) of a
+    weighted-geometry handle: replays equal the oracle's weighted descriptors
+    and its 2-NN."""
+    from paper_1609_03986_amd.binding import Latch, image_table
+    torch = torch_cuda
+    w = synth.gaussian_weights(8, 2.0, 128)
+    trip = synth.triplet_table_geom(64, 8)
+    g = np.random.default_rng(23)
+    imgs = [synth.smoothed_noise(g, 200, 260), synth.smoothed_noise(g, 150, 300)]
+    counts = [900, 700]
+    kps = np.concatenate([synth.random_keypoints(g, c, *im.shape, margin=-5) for c, im in zip(counts, imgs)])
+    ids = np.repeat(np.arange(2, dtype=np.int32), counts)
+    pairs = np.array([[0, counts[0], counts[0], counts[1], 0]], np.int64)
+    lat = Latch(trip, 64, 8, w)
+    try:
+        dimgs = [torch.from_numpy(im).cuda() for im in imgs]
+        table = image_table(dimgs)
+        dk, di = torch.from_numpy(kps).cuda(), torch.from_numpy(ids).cuda()
+        desc = torch.zeros((len(kps), 16), dtype=torch.int32, device="cuda")
+        dp = torch.from_numpy(pairs).cuda()
+        idx = torch.zeros((len(kps), 2), dtype=torch.int32, device="cuda")
+        dist = torch.zeros_like(idx)
+        acc = torch.zeros(len(kps), dtype=torch.uint8, device="cuda")
+        plan = lat.plan(table, 2, di, dk, desc, dp, idx, dist, acc)
+        try:
+            for rep in range(3):
+                desc.fill_(-1)
+                idx.fill_(-7)
+                torch.cuda.synchronize()
+                plan.run()
+                torch.cuda.synchronize()
+                D = desc.cpu().numpy().view(np.uint32)
+                for i, im in enumerate(imgs):
+                    sel = np.nonzero(ids == i)[0]
+                    want, _ = oracle.extract_geom(im, kps[sel], trip, 64, 8, w)
+                    assert np.array_equal(D[sel], want), (rep, i)
+                wi, wd, wa = oracle.knn(D[:counts[0]], D[counts[0]:])
+                assert np.array_equal(idx.cpu().numpy()[:counts[0]], wi), rep
+                assert np.array_equal(acc.cpu().numpy()[:counts[0]], wa), rep
+        finally:
+            plan.close()
+    finally:
+        lat.close()
