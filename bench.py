@@ -16,7 +16,7 @@ latency percentiles, per-kernel durations from HIP events recorded by the
 library on its launch stream, the roofline of the dominant kernel and the
 CPU oracle baseline.
 
-    python bench.py [--gpus 1] [--steps 50] [--warmup 5] [--path mfma|popcount]
+    python bench.py [--gpus 1] [--steps 500] [--warmup 300] [--path mfma|fp4|popcount]
 """
 import argparse
 import json
@@ -63,8 +63,10 @@ PEAK_INT_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0         # 39.3
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    # Defaults: 300 untimed steps (about 40 ms) bring the GPU to its steady
+    # clocks before the 500 timed ones (about 60 ms).
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=300)
     ap.add_argument("--path", default="auto", choices=["auto", "mfma", "fp4", "popcount"],
                     help="matcher path of the step (auto: the handle's tuning table)")
     ap.add_argument("--cpu-seconds", type=float, default=10.0,
@@ -272,7 +274,7 @@ def main():
         lat.extract_dense(img_q, 0, 0, W_img, H_img, dq)
         lat.extract_dense(img_t, 0, 0, W_img, H_img, dt)
 
-    dense_steps = max(3, args.steps // 5)
+    dense_steps = max(3, min(args.steps // 5, 20))
     de_wall, _ = timed_loop(dense_both, dense_steps, 1)
     dm_wall, _ = timed_loop(lambda: lat.knn_window(dq, dt, W_img, H_img, DENSE_RADIUS), dense_steps, 1)
     lat.timing(True)
