@@ -1,0 +1,72 @@
+"""GPU parity at the full sizes of the batched workloads (the SfM batch: 64
+crops of 3000x2000 with 20,000 keypoints each and 63 consecutive 20k x 20k
+pairs; the uneven batch: 256 images of the size mix, log-normal keypoint
+counts), in one batched extraction and one batched matching launch: 1,000
+sampled descriptors against the oracle's extraction and 1,000 sampled queries
+against the oracle's brute force over their pair's whole train range."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_03986_amd import batchbench
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def run_full(torch, triplets, imgs, kps, seed):
+    from paper_1609_03986_amd.binding import Latch, image_table, pair_table
+    lat = Latch(triplets)
+    try:
+        counts = [len(k) for k in kps]
+        first = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+        total = int(sum(counts))
+        dimgs = [torch.from_numpy(im).cuda() for im in imgs]
+        kp_all = np.concatenate(kps).astype(np.float32)
+        ids = np.repeat(np.arange(len(imgs), dtype=np.int32), counts)
+        desc = lat.extract_batch(image_table(dimgs), len(imgs), torch.from_numpy(ids).cuda(),
+                                 torch.from_numpy(kp_all).cuda())
+        pairs = np.array([(first[i], counts[i], first[i + 1], counts[i + 1], first[i])
+                          for i in range(len(imgs) - 1)], np.int64)
+        idx, dist, acc = lat.knn_batch(desc, desc, pair_table(pairs), total)
+        torch.cuda.synchronize()
+        assert lat.check_errors(clear=True) == 0
+        D = desc.cpu().numpy().view(np.uint32)
+        idx, dist, acc = idx.cpu().numpy(), dist.cpu().numpy(), acc.cpu().numpy()
+    finally:
+        lat.close()
+    g = np.random.default_rng(seed)
+    # 1,000 descriptors, spread over the images.
+    sel = np.sort(g.choice(total, 1000, replace=False))
+    for i in np.unique(ids[sel]):
+        s = sel[ids[sel] == i]
+        want, f = oracle.extract(imgs[i], kp_all[s], triplets)
+        assert f == 0 and np.array_equal(D[s], want), int(i)
+    # 1,000 queries of the pairs (queries of the last image have no pair).
+    q_sel = np.sort(g.choice(first[-1], 1000, replace=False))
+    for i in np.unique(ids[q_sel]):
+        qs = q_sel[ids[q_sel] == i]
+        tf, nt = first[i + 1], counts[i + 1]
+        wi, wd, wa = oracle.knn(D[qs], D[tf:tf + nt])
+        assert np.array_equal(idx[qs], wi), int(i)
+        assert np.array_equal(dist[qs], wd), int(i)
+        assert np.array_equal(acc[qs], wa), int(i)
+
+
+def test_sfm_batch_full_size(torch_cuda, triplets):
+    imgs, kps = batchbench.sfm_workload()
+    assert len(imgs) == 64 and imgs[0].shape == (2000, 3000) and len(kps[0]) == 20000
+    run_full(torch_cuda, triplets, imgs, kps, 1)
+
+
+def test_uneven_batch_full_size(torch_cuda, triplets):
+    imgs, kps = batchbench.uneven_workload()
+    assert len(imgs) == 256
+    run_full(torch_cuda, triplets, imgs, kps, 2)
