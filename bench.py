@@ -368,11 +368,34 @@ def main():
         oracle.knn(oq, ot, k=2, ratio=0.8)
         t_one = time.perf_counter() - t0
         oracle.set_threads(cores)
+        # The oracle on bounded samples of the components, all host cores.
+        def rate(fn, units):
+            t0 = time.perf_counter()
+            fn()
+            return units / (time.perf_counter() - t0)
+        geo_sample = np.concatenate([w["query_kps"], w["train_kps"]])[:2000]
+        comp = {
+            "detection_images_per_s": rate(lambda: oracle.detect(w["query_image"], DETECT_THRESHOLD), 1),
+            "weighted_extraction_desc_per_s": rate(
+                lambda: oracle.extract_geom(w["query_image"], geo_sample, geo_trip, 64, 8,
+                                            synth.gaussian_weights(8, 2.0, 128)), len(geo_sample)),
+            "dense_extraction_desc_per_s": rate(
+                lambda: oracle.extract_dense(w["query_image"], 900, 500, 64, 32, trip), 64 * 32),
+        }
+        dq_s = oracle.extract_dense(w["query_image"], 900, 500, 64, 32, trip)
+        dt_s = oracle.extract_dense(w["train_image"], 900, 500, 64, 32, trip)
+        comp["dense_match_pairs_per_s"] = rate(
+            lambda: oracle.knn_window(dq_s, dt_s, 64, 32, DENSE_RADIUS),
+            sum(min(32, y + DENSE_RADIUS + 1) - max(0, y - DENSE_RADIUS) for y in range(32)) *
+            sum(min(64, x + DENSE_RADIUS + 1) - max(0, x - DENSE_RADIUS) for x in range(64)))
         cpu = {"value": (nq + nt) * reps / t_cpu, "unit": "desc/s", "cores": cores,
                "kind": "oracle",
-               "sample": "%d whole steps (2 x 10,000 extractions + 10,000 x 10,000 2-NN) in %.1f s"
-                         % (reps, t_cpu),
-               "value_1_core": (nq + nt) / t_one}
+               "sample": "%d whole steps (2 x 10,000 extractions + 10,000 x 10,000 2-NN) in %.1f s; "
+                         "components: detection of one 1920x1080 image, weighted extraction of "
+                         "2,000 keypoints, dense extraction and radius-%d matching of a 64x32 "
+                         "region" % (reps, t_cpu, DENSE_RADIUS),
+               "value_1_core": (nq + nt) / t_one,
+               "components": comp}
 
     out = {
         "metric": METRIC, "value": value, "unit": "desc/s", "n_gpus": 1, "steps": args.steps,
