@@ -40,6 +40,14 @@ __device__ __forceinline__ int mul24(int a, int b)
     return r;
 }
 
+// a b + c with 24-bit signed a, b (b an inline constant here).
+__device__ __forceinline__ int mad24(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "v"(a), "i"(b), "v"(c));
+    return r;
+}
+
 // 1 if h > 0, else 0, in one instruction (median of h, 0 and 1).
 __device__ __forceinline__ uint32_t bit_of(int h)
 {
@@ -111,7 +119,7 @@ __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
 #pragma unroll
             for (int rr = 0; rr < kDRegionRows; ++rr) {
                 const int a = pa[rr * kDTexStride], c1 = p1[rr * kDTexStride], c2 = p2[rr * kDTexStride];
-                const int g = mul24(c1 - c2, c1 + c2 - 2 * a);
+                const int g = mul24(c1 - c2, mad24(a, -2, c1 + c2));
                 ring[rr % 7] = g;
                 s += g;
                 if (rr >= 6) {
