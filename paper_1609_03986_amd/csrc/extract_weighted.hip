@@ -17,8 +17,11 @@
 //      thread, issued one keypoint ahead), written to LDS as 16-bit pixels
 //      in four copies shifted by 0..3 columns, so that the 8 pixels of any
 //      patch row start on a quadword of one copy (one ds_read2_b64);
-//   3. two triplets per thread; one ballot per wavefront and triplet set
-//      gives 64 bits.
+//   3. two triplets per thread: wavefront w evaluates triplets 64 w + l and
+//      256 + 64 w + l (l = 0..63) in two rounds, in (round, lane) slots the
+//      host chose so that the 16-lane groups of a ds_read2_b64 hit few bank
+//      conflicts; a ballot per round gives 64 bits, and four ballot words per
+//      wavefront in LDS put them back in triplet order.
 #include "internal.h"
 
 namespace latch {
@@ -111,11 +114,13 @@ __device__ __forceinline__ bool weighted_bit(const uint8_t *lds, uint32_t oa, ui
 template <bool kTable, int kW>
 __global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
     ImageSource src, const float4 *__restrict__ kps, int64_t n_host, const int64_t *__restrict__ n_dev,
-    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off, WeightRows w,
-    uint32_t *__restrict__ desc, uint32_t *__restrict__ flags)
+    const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off,
+    const uint32_t *__restrict__ unperm, WeightRows w, uint32_t *__restrict__ desc,
+    uint32_t *__restrict__ flags)
 {
     using G = WGeom<kW>;
     __shared__ __attribute__((aligned(16))) uint8_t lds[G::kLds];
+    __shared__ uint32_t ballot_words[4 * (kWThreads / 64)];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -123,8 +128,11 @@ __global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
     // The spare columns and row stay zero (they meet zero weights only).
     for (int i = tid; i < G::kLds / 4; i += kWThreads) reinterpret_cast<uint32_t *>(lds)[i] = 0u;
 
-    // Triplets tid and 256 + tid: bits 64 wave + lane of words 0..7 and 8..15.
-    const uint2 t0 = trip_off[tid], t1 = trip_off[kWThreads + tid];
+    // This lane's slots in rounds 0 and 1, and the slots of its output bits
+    // (triplets 64 wave + lane and 256 + 64 wave + lane).
+    const uint2 t0 = trip_off[128 * wave + lane], t1 = trip_off[128 * wave + 64 + lane];
+    const uint32_t un = unperm[64 * wave + lane];
+    uint32_t *bw = ballot_words + 4 * wave;
 
     int64_t n = n_host;
     if (n_dev) n = min(n, *n_dev);
@@ -157,9 +165,18 @@ __global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
 
         const uint64_t b0 = __ballot(weighted_bit<kW>(lds, t0.x & 0xffffu, t0.x >> 16, t0.y, w));
         const uint64_t b1 = __ballot(weighted_bit<kW>(lds, t1.x & 0xffffu, t1.x >> 16, t1.y, w));
+        // Slot order -> triplet order through this wavefront's ballot words
+        // (written and read by the same wavefront, so in order).
         if (lane < 4) {
             const uint64_t b = lane < 2 ? b0 : b1;
-            const uint32_t word = (uint32_t)(lane & 1 ? b >> 32 : b);
+            bw[lane] = (uint32_t)(lane & 1 ? b >> 32 : b);
+        }
+        const uint32_t s0 = un & 0xffu, s1 = (un >> 8) & 0xffu;
+        const uint64_t o0 = __ballot((bw[s0 >> 5] >> (s0 & 31u)) & 1u);
+        const uint64_t o1 = __ballot((bw[s1 >> 5] >> (s1 & 31u)) & 1u);
+        if (lane < 4) {
+            const uint64_t o = lane < 2 ? o0 : o1;
+            const uint32_t word = (uint32_t)(lane & 1 ? o >> 32 : o);
             desc[p * kWords + 8 * (lane >> 1) + 2 * wave + (lane & 1)] = word;
         }
     }
@@ -174,12 +191,12 @@ hipError_t launch_weighted_w(const ExtractArgs &a, hipStream_t stream)
     ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
     if (a.table)
         hipLaunchKernelGGL((extract_weighted_kernel<true, kW>), dim3((unsigned)blocks), dim3(kWThreads),
-                           0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off, a.weights,
+                           0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off, a.wunperm, a.weights,
                            a.desc, a.flags);
     else
         hipLaunchKernelGGL((extract_weighted_kernel<false, kW>), dim3((unsigned)blocks),
                            dim3(kWThreads), 0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off,
-                           a.weights, a.desc, a.flags);
+                           a.wunperm, a.weights, a.desc, a.flags);
     return hipGetLastError();
 }
 

@@ -81,7 +81,8 @@ struct ExtractArgs {
     int num_cus;
     // Weighted geometry (window 0: the default 48 x 48, 7 x 7, unit weights).
     int window = 0;
-    const uint2 *wtrip_off = nullptr;   // [512] in triplet order: LDS byte offsets of the patches
+    const uint2 *wtrip_off = nullptr;   // [512] by slot: LDS byte offsets of the patches
+    const uint32_t *wunperm = nullptr;  // [256] per (wavefront, lane): slots of its two output bits
     WeightRows weights = {};
 };
 

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <array>
 #include <vector>
 
 #include "../../include/latch.h"
@@ -21,7 +22,8 @@ struct latch_ctx {
     uint32_t *flags_dev = nullptr;     // sticky error word
     // Weighted geometry (latch_create_geometry); window 0 runs the default kernel.
     int window = 0;
-    uint2 *wtrip_dev = nullptr;        // [512] in triplet order: weighted-kernel patch offsets
+    uint2 *wtrip_dev = nullptr;        // [512] by slot: weighted-kernel patch offsets
+    uint32_t *wunperm_dev = nullptr;   // [256] per (wavefront, lane): slots of its two output bits
     uint2 *dense_off_dev = nullptr;    // [512] in triplet order: dense-kernel texture offsets
     WeightRows weights = {};
     uint8_t *ws = nullptr;             // grow-only workspace
@@ -90,9 +92,9 @@ uint32_t patch_offset(int r, int c)
     return (uint32_t)(kEdgeBase + 8 * (x - 8 * kCopyQwords) + y * kCopyRowBytes + 8 * (kCopyQwords - 1));
 }
 
-// Slot assignment of the extraction kernel.  Wavefront w evaluates triplets
-// 256 w .. 256 w + 255 in 4 rounds of 64 lanes; slot 64 r + l is lane l of
-// round r.  A ds_read2_b64 of a wavefront is served 16 lanes at a time, and
+// Slot assignment of the extraction kernels.  Wavefront w evaluates
+// `per_wave` triplets (members 0 .. per_wave - 1 of toff[per_wave w ..]) in
+// rounds of 64 lanes; slot 64 r + l is lane l of round r.  A ds_read2_b64 of a wavefront is served 16 lanes at a time, and
 // those 16 lanes read without bank conflicts when their quadword addresses
 // differ mod 16 (measured on gfx950; random addresses take about 2.5 times
 // as long).  Every patch row read of a lane is its patch offset plus a
@@ -100,21 +102,22 @@ uint32_t patch_offset(int r, int c)
 // offset.  A deterministic annealing search over swaps puts triplets into
 // the 16 lane groups of a wavefront so that, per group and per patch (anchor,
 // companion 1, companion 2), the largest number of lanes sharing a bank is
-// as small as it gets.  slot_of[t] is the slot (within its wavefront) of
-// triplet t; results never depend on it, only speed does.
-void assign_slots(const uint2 *toff, uint8_t *slot_of)
+// as small as it gets.  slot_of[per_wave w + i] is the slot (within its
+// wavefront) of member i; results never depend on it, only speed does.
+void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
 {
     constexpr int kIters = 600000;
-    for (int w = 0; w < 2; ++w) {
-        int col[256][3];
-        for (int i = 0; i < 256; ++i) {
-            const uint2 o = toff[256 * w + i];
+    for (int w = 0; w < waves; ++w) {
+        std::vector<std::array<int, 3>> col(per_wave);
+        for (int i = 0; i < per_wave; ++i) {
+            const uint2 o = toff[per_wave * w + i];
             const uint32_t off[3] = {o.x & 0xffffu, o.x >> 16, o.y};
             for (int k = 0; k < 3; ++k) col[i][k] = (int)((off[k] >> 3) & 15u);
         }
-        int group_of[256], cnt[16][3][16];
+        std::vector<int> group_of(per_wave);
+        int cnt[16][3][16];
         std::memset(cnt, 0, sizeof cnt);
-        for (int i = 0; i < 256; ++i) {
+        for (int i = 0; i < per_wave; ++i) {
             group_of[i] = i / 16;
             for (int k = 0; k < 3; ++k) ++cnt[group_of[i]][k][col[i][k]];
         }
@@ -131,7 +134,7 @@ void assign_slots(const uint2 *toff, uint8_t *slot_of)
             return rs;
         };
         for (int it = 0; it < kIters; ++it) {
-            const int i = (int)(rnd() & 255u), j = (int)(rnd() & 255u);
+            const int i = (int)(rnd() % (uint32_t)per_wave), j = (int)(rnd() % (uint32_t)per_wave);
             const int G = group_of[i], H = group_of[j];
             if (G == H) continue;
             int before = 0, after = 0, sq = 0;
@@ -169,9 +172,9 @@ void assign_slots(const uint2 *toff, uint8_t *slot_of)
         }
         // Group g = 4 r + h is lanes 16 h .. 16 h + 15 of round r.
         int fill[16] = {0};
-        for (int i = 0; i < 256; ++i) {
+        for (int i = 0; i < per_wave; ++i) {
             const int g = group_of[i];
-            slot_of[256 * w + i] = (uint8_t)(64 * (g >> 2) + 16 * (g & 3) + fill[g]++);
+            slot_of[per_wave * w + i] = (uint8_t)(64 * (g >> 2) + 16 * (g & 3) + fill[g]++);
         }
     }
 }
@@ -341,6 +344,7 @@ ExtractArgs batch_extract_args(latch_handle h, const latch_image *images_dev, in
     a.num_cus = h->num_cus;
     a.window = h->window;
     a.wtrip_off = h->wtrip_dev;
+    a.wunperm = h->wunperm_dev;
     a.weights = h->weights;
     return a;
 }
@@ -418,7 +422,7 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
     // Triplets by slot, and per (wavefront w, lane l) the slots of output
     // bits 256 w + 64 k + l, k = 0..3, one byte each.
     uint8_t slot_of[kTriplets];
-    assign_slots(toff, slot_of);
+    assign_slots(toff, 2, 256, slot_of);
     uint2 toff_slot[kTriplets];
     uint32_t unperm[2 * 64] = {};
     for (int t = 0; t < kTriplets; ++t) {
@@ -488,9 +492,28 @@ int latch_create_geometry(latch_handle *out, const uint8_t *triplets_host, int w
             o[k] = weighted_patch_offset(window, tr[2 * k] - patch / 2, tr[2 * k + 1] - patch / 2);
         toff[t] = make_uint2(o[0] | (o[1] << 16), o[2]);
     }
+    // Wavefront w evaluates triplets 64 w + l and 256 + 64 w + l (members l
+    // and 64 + l) in two rounds; bank-aware slots, and per lane the slots of
+    // its two output bits.
+    const int kWWaves = 4, kWPerWave = kTriplets / kWWaves;
+    auto member = [](int w, int i) { return i < 64 ? 64 * w + i : 256 + 64 * w + (i - 64); };
+    uint2 mem[kTriplets];
+    for (int w = 0; w < kWWaves; ++w)
+        for (int i = 0; i < kWPerWave; ++i) mem[kWPerWave * w + i] = toff[member(w, i)];
+    uint8_t slot_of[kTriplets];
+    assign_slots(mem, kWWaves, kWPerWave, slot_of);
+    uint2 toff_slot[kTriplets];
+    uint32_t unperm[kWWaves * 64] = {};
+    for (int w = 0; w < kWWaves; ++w)
+        for (int i = 0; i < kWPerWave; ++i) {
+            toff_slot[kWPerWave * w + slot_of[kWPerWave * w + i]] = mem[kWPerWave * w + i];
+            unperm[64 * w + (i & 63)] |= (uint32_t)slot_of[kWPerWave * w + i] << (8 * (i >> 6));
+        }
     hipError_t e;
-    if ((e = hipMalloc((void **)&h->wtrip_dev, sizeof toff)) != hipSuccess ||
-        (e = hipMemcpy(h->wtrip_dev, toff, sizeof toff, hipMemcpyHostToDevice)) != hipSuccess ||
+    if ((e = hipMalloc((void **)&h->wtrip_dev, sizeof toff_slot)) != hipSuccess ||
+        (e = hipMalloc((void **)&h->wunperm_dev, sizeof unperm)) != hipSuccess ||
+        (e = hipMemcpy(h->wtrip_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(h->wunperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipDeviceSynchronize()) != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
         latch_destroy(h);
@@ -509,6 +532,7 @@ void latch_destroy(latch_handle h)
     if (h->unperm_dev) (void)hipFree(h->unperm_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
     if (h->wtrip_dev) (void)hipFree(h->wtrip_dev);
+    if (h->wunperm_dev) (void)hipFree(h->wunperm_dev);
     if (h->dense_off_dev) (void)hipFree(h->dense_off_dev);
     if (h->ws) (void)hipFree(h->ws);
     release_timed(h);
@@ -552,6 +576,7 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.num_cus = h->num_cus;
     a.window = h->window;
     a.wtrip_off = h->wtrip_dev;
+    a.wunperm = h->wunperm_dev;
     a.weights = h->weights;
     hipError_t e = timed_launch(h, "extract", stream, [&] { return run_extract(a, stream); });
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "extract launch");
