@@ -6,6 +6,8 @@
 #include <cstring>
 #include <string>
 #include <array>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "../../include/latch.h"
@@ -104,9 +106,9 @@ uint32_t patch_offset(int r, int c)
 // companion 1, companion 2), the largest number of lanes sharing a bank is
 // as small as it gets.  slot_of[per_wave w + i] is the slot (within its
 // wavefront) of member i; results never depend on it, only speed does.
-void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
+void search_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
 {
-    constexpr int kIters = 600000;
+    constexpr int kIters = 3000000;
     for (int w = 0; w < waves; ++w) {
         std::vector<std::array<int, 3>> col(per_wave);
         for (int i = 0; i < per_wave; ++i) {
@@ -177,6 +179,34 @@ void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
             slot_of[per_wave * w + i] = (uint8_t)(64 * (g >> 2) + 16 * (g & 3) + fill[g]++);
         }
     }
+}
+
+// search_slots takes a few hundred milliseconds; its result depends only on
+// the offsets, so it is kept per process for each offset table.
+void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
+{
+    static std::mutex mu;
+    static std::map<std::vector<uint32_t>, std::vector<uint8_t>> cache;
+    const int n = waves * per_wave;
+    std::vector<uint32_t> key;
+    key.reserve(2 * n + 2);
+    key.push_back((uint32_t)waves);
+    key.push_back((uint32_t)per_wave);
+    for (int i = 0; i < n; ++i) {
+        key.push_back(toff[i].x);
+        key.push_back(toff[i].y);
+    }
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            std::memcpy(slot_of, it->second.data(), (size_t)n);
+            return;
+        }
+    }
+    search_slots(toff, waves, per_wave, slot_of);
+    std::lock_guard<std::mutex> lock(mu);
+    cache.emplace(std::move(key), std::vector<uint8_t>(slot_of, slot_of + n));
 }
 
 int ensure_workspace(latch_handle h, size_t need)
