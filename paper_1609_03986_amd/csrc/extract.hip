@@ -17,8 +17,8 @@
 //   4. Eq. 1 (Sec. 3.1) for 512 triplets: each wavefront takes 4 rounds of 64
 //      lanes, one triplet per lane per round, in exact integer arithmetic;
 //   5. a 64-bit ballot per round packs the bits.  Triplets sit in (round,
-//      lane) slots chosen on the host so that the 16-lane groups of a
-//      ds_read2_b64 hit few bank conflicts; four table lookups and ballots
+//      lane) slots chosen on the host so that the 32-lane halves of a
+//      ds_read_b64 hit few bank conflicts; four table lookups and ballots
 //      put the bits back in triplet order, and 8 lanes per wavefront store
 //      its 8 words.
 //
@@ -275,14 +275,55 @@ struct Rows {
     uint2 a[7], c[7], e[7];
 };
 
+// The 21 patch rows of a triplet, each one ds_read_b64, then a wait for all
+// of them.  Written out because the compiler would pair rows k and k + 1 of
+// a patch into a ds_read2_b64, which gfx950 serves 16 lanes and one address
+// at a time (at best half the rate of two ds_read_b64, and bank-conflicted
+// unless the 16-lane quarters, rather than the 32-lane halves, of a wavefront
+// are spread over the banks).  Every address is a host-checked patch offset
+// plus a row offset inside the copies.
 __device__ __forceinline__ void load_rows(const uint8_t *lds, uint32_t oa, uint32_t o1, uint32_t o2,
                                           Rows &r)
 {
+    static_assert(kCopyRowBytes == 40, "row offsets below");
+    const uint32_t base = (uint32_t)(uintptr_t)lds;
+    uint64_t a0, a1, a2, a3, a4, a5, a6, c0, c1, c2, c3, c4, c5, c6, e0, e1, e2, e3, e4, e5, e6;
+    asm volatile(
+        "ds_read_b64 %0, %21\n"
+        "ds_read_b64 %7, %22\n"
+        "ds_read_b64 %14, %23\n"
+        "ds_read_b64 %1, %21 offset:40\n"
+        "ds_read_b64 %8, %22 offset:40\n"
+        "ds_read_b64 %15, %23 offset:40\n"
+        "ds_read_b64 %2, %21 offset:80\n"
+        "ds_read_b64 %9, %22 offset:80\n"
+        "ds_read_b64 %16, %23 offset:80\n"
+        "ds_read_b64 %3, %21 offset:120\n"
+        "ds_read_b64 %10, %22 offset:120\n"
+        "ds_read_b64 %17, %23 offset:120\n"
+        "ds_read_b64 %4, %21 offset:160\n"
+        "ds_read_b64 %11, %22 offset:160\n"
+        "ds_read_b64 %18, %23 offset:160\n"
+        "ds_read_b64 %5, %21 offset:200\n"
+        "ds_read_b64 %12, %22 offset:200\n"
+        "ds_read_b64 %19, %23 offset:200\n"
+        "ds_read_b64 %6, %21 offset:240\n"
+        "ds_read_b64 %13, %22 offset:240\n"
+        "ds_read_b64 %20, %23 offset:240\n"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a0), "=&v"(a1), "=&v"(a2), "=&v"(a3), "=&v"(a4), "=&v"(a5), "=&v"(a6),
+          "=&v"(c0), "=&v"(c1), "=&v"(c2), "=&v"(c3), "=&v"(c4), "=&v"(c5), "=&v"(c6),
+          "=&v"(e0), "=&v"(e1), "=&v"(e2), "=&v"(e3), "=&v"(e4), "=&v"(e5), "=&v"(e6)
+        : "v"(base + oa), "v"(base + o1), "v"(base + o2)
+        : "memory");
+    const uint64_t a[7] = {a0, a1, a2, a3, a4, a5, a6};
+    const uint64_t c[7] = {c0, c1, c2, c3, c4, c5, c6};
+    const uint64_t e[7] = {e0, e1, e2, e3, e4, e5, e6};
 #pragma unroll
     for (int k = 0; k < 2 * kPatchR + 1; ++k) {
-        r.a[k] = *reinterpret_cast<const uint2 *>(lds + oa + kCopyRowBytes * k);
-        r.c[k] = *reinterpret_cast<const uint2 *>(lds + o1 + kCopyRowBytes * k);
-        r.e[k] = *reinterpret_cast<const uint2 *>(lds + o2 + kCopyRowBytes * k);
+        r.a[k] = make_uint2((uint32_t)a[k], (uint32_t)(a[k] >> 32));
+        r.c[k] = make_uint2((uint32_t)c[k], (uint32_t)(c[k] >> 32));
+        r.e[k] = make_uint2((uint32_t)e[k], (uint32_t)(e[k] >> 32));
     }
 }
 

@@ -96,17 +96,24 @@ uint32_t patch_offset(int r, int c)
 
 // Slot assignment of the extraction kernels.  Wavefront w evaluates
 // `per_wave` triplets (members 0 .. per_wave - 1 of toff[per_wave w ..]) in
-// rounds of 64 lanes; slot 64 r + l is lane l of round r.  A ds_read2_b64 of a wavefront is served 16 lanes at a time, and
-// those 16 lanes read without bank conflicts when their quadword addresses
-// differ mod 16 (measured on gfx950; random addresses take about 2.5 times
-// as long).  Every patch row read of a lane is its patch offset plus a
-// uniform row offset, so the bank of all 7 rows follows from the patch
-// offset.  A deterministic annealing search over swaps puts triplets into
-// the 16 lane groups of a wavefront so that, per group and per patch (anchor,
-// companion 1, companion 2), the largest number of lanes sharing a bank is
-// as small as it gets.  slot_of[per_wave w + i] is the slot (within its
-// wavefront) of member i; results never depend on it, only speed does.
-void search_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
+// rounds of 64 lanes; slot 64 r + l is lane l of round r.  On gfx950 (measured
+// with a probe over random and structured address patterns):
+//  * a ds_read_b64 is served 32 lanes at a time over 64 dword banks, so its
+//    32-lane halves read without conflicts when their quadword addresses
+//    differ mod 32;
+//  * a ds_read2_b64 is served 16 lanes and one address at a time over 32
+//    banks, so its 16-lane quarters read without conflicts when their
+//    quadword addresses differ mod 16.
+// `group` (lanes served together) and `cols` (quadword banks) name the
+// model of the kernel's row reads.  Every patch row read of a lane is its
+// patch offset plus a uniform row offset, so the bank of all rows follows
+// from the patch offset.  A deterministic annealing search over swaps puts
+// triplets into the lane groups of a wavefront so that, per group and per
+// patch (anchor, companion 1, companion 2), the largest number of lanes
+// sharing a bank is as small as it gets.  slot_of[per_wave w + i] is the
+// slot (within its wavefront) of member i; results never depend on it, only
+// speed does.
+void search_slots(const uint2 *toff, int waves, int per_wave, int group, int cols, uint8_t *slot_of)
 {
     constexpr int kIters = 3000000;
     for (int w = 0; w < waves; ++w) {
@@ -114,18 +121,18 @@ void search_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
         for (int i = 0; i < per_wave; ++i) {
             const uint2 o = toff[per_wave * w + i];
             const uint32_t off[3] = {o.x & 0xffffu, o.x >> 16, o.y};
-            for (int k = 0; k < 3; ++k) col[i][k] = (int)((off[k] >> 3) & 15u);
+            for (int k = 0; k < 3; ++k) col[i][k] = (int)((off[k] >> 3) & (uint32_t)(cols - 1));
         }
         std::vector<int> group_of(per_wave);
-        int cnt[16][3][16];
+        int cnt[16][3][32];
         std::memset(cnt, 0, sizeof cnt);
         for (int i = 0; i < per_wave; ++i) {
-            group_of[i] = i / 16;
+            group_of[i] = i / group;
             for (int k = 0; k < 3; ++k) ++cnt[group_of[i]][k][col[i][k]];
         }
         auto gmax = [&](int g, int k) {
             int m = 0;
-            for (int c = 0; c < 16; ++c) m = cnt[g][k][c] > m ? cnt[g][k][c] : m;
+            for (int c = 0; c < cols; ++c) m = cnt[g][k][c] > m ? cnt[g][k][c] : m;
             return m;
         };
         uint32_t rs = 0x9e3779b9u + (uint32_t)w;
@@ -172,26 +179,30 @@ void search_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
                 }
             }
         }
-        // Group g = 4 r + h is lanes 16 h .. 16 h + 15 of round r.
+        // Group g = (64 / group) r + h is lanes group h .. group (h + 1) - 1
+        // of round r.
+        const int per_round = 64 / group;
         int fill[16] = {0};
         for (int i = 0; i < per_wave; ++i) {
             const int g = group_of[i];
-            slot_of[per_wave * w + i] = (uint8_t)(64 * (g >> 2) + 16 * (g & 3) + fill[g]++);
+            slot_of[per_wave * w + i] = (uint8_t)(64 * (g / per_round) + group * (g % per_round) + fill[g]++);
         }
     }
 }
 
 // search_slots takes a few hundred milliseconds; its result depends only on
 // the offsets, so it is kept per process for each offset table.
-void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
+void assign_slots(const uint2 *toff, int waves, int per_wave, int group, int cols, uint8_t *slot_of)
 {
     static std::mutex mu;
     static std::map<std::vector<uint32_t>, std::vector<uint8_t>> cache;
     const int n = waves * per_wave;
     std::vector<uint32_t> key;
-    key.reserve(2 * n + 2);
+    key.reserve(2 * n + 4);
     key.push_back((uint32_t)waves);
     key.push_back((uint32_t)per_wave);
+    key.push_back((uint32_t)group);
+    key.push_back((uint32_t)cols);
     for (int i = 0; i < n; ++i) {
         key.push_back(toff[i].x);
         key.push_back(toff[i].y);
@@ -204,7 +215,7 @@ void assign_slots(const uint2 *toff, int waves, int per_wave, uint8_t *slot_of)
             return;
         }
     }
-    search_slots(toff, waves, per_wave, slot_of);
+    search_slots(toff, waves, per_wave, group, cols, slot_of);
     std::lock_guard<std::mutex> lock(mu);
     cache.emplace(std::move(key), std::vector<uint8_t>(slot_of, slot_of + n));
 }
@@ -452,7 +463,7 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
     // Triplets by slot, and per (wavefront w, lane l) the slots of output
     // bits 256 w + 64 k + l, k = 0..3, one byte each.
     uint8_t slot_of[kTriplets];
-    assign_slots(toff, 2, 256, slot_of);
+    assign_slots(toff, 2, 256, 32, 32, slot_of);   // row reads: ds_read_b64
     uint2 toff_slot[kTriplets];
     uint32_t unperm[2 * 64] = {};
     for (int t = 0; t < kTriplets; ++t) {
@@ -531,7 +542,7 @@ int latch_create_geometry(latch_handle *out, const uint8_t *triplets_host, int w
     for (int w = 0; w < kWWaves; ++w)
         for (int i = 0; i < kWPerWave; ++i) mem[kWPerWave * w + i] = toff[member(w, i)];
     uint8_t slot_of[kTriplets];
-    assign_slots(mem, kWWaves, kWPerWave, slot_of);
+    assign_slots(mem, kWWaves, kWPerWave, 16, 16, slot_of);   // row reads: ds_read2_b64
     uint2 toff_slot[kTriplets];
     uint32_t unperm[kWWaves * 64] = {};
     for (int w = 0; w < kWWaves; ++w)
