@@ -16,10 +16,10 @@
 //   2. the W x W window gathered with the rule (W * W / 256 samples per
 //      thread, issued one keypoint ahead), written to LDS as 16-bit pixels
 //      in four copies shifted by 0..3 columns, so that the 8 pixels of any
-//      patch row start on a quadword of one copy (one ds_read2_b64);
+//      patch row start on a quadword of one copy (two ds_read_b64);
 //   3. two triplets per thread: wavefront w evaluates triplets 64 w + l and
 //      256 + 64 w + l (l = 0..63) in two rounds, in (round, lane) slots the
-//      host chose so that the 16-lane groups of a ds_read2_b64 hit few bank
+//      host chose so that the 32-lane halves of a ds_read_b64 hit few bank
 //      conflicts; a ballot per round gives 64 bits, and four ballot words per
 //      wavefront in LDS put them back in triplet order.
 #include "internal.h"
@@ -82,32 +82,77 @@ __device__ __forceinline__ void write_window(uint8_t *lds, int tid, const uint32
     }
 }
 
+// Rows r and r + 1 of the three patches (two quadwords each) as twelve single
+// ds_read_b64, then a wait for all of them: v[6 k + 2 p + h] is quadword h
+// of row r + k of patch p (anchor, companion 1, companion 2).  Written out
+// because the compiler would pair the quadwords into ds_read2_b64, which
+// gfx950 serves 16 lanes and one address at a time (at best half the rate of
+// two ds_read_b64).  Every address is a host-checked patch offset plus a row
+// offset inside the copies.
+template <int kOff, int kRowBytes>
+__device__ __forceinline__ void load_row_pair(uint32_t pa, uint32_t pc, uint32_t pe, uint64_t (&v)[12])
+{
+    asm volatile(
+        "ds_read_b64 %0, %12 offset:%15\n"
+        "ds_read_b64 %1, %12 offset:%16\n"
+        "ds_read_b64 %2, %13 offset:%15\n"
+        "ds_read_b64 %3, %13 offset:%16\n"
+        "ds_read_b64 %4, %14 offset:%15\n"
+        "ds_read_b64 %5, %14 offset:%16\n"
+        "ds_read_b64 %6, %12 offset:%17\n"
+        "ds_read_b64 %7, %12 offset:%18\n"
+        "ds_read_b64 %8, %13 offset:%17\n"
+        "ds_read_b64 %9, %13 offset:%18\n"
+        "ds_read_b64 %10, %14 offset:%17\n"
+        "ds_read_b64 %11, %14 offset:%18\n"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(v[0]), "=&v"(v[1]), "=&v"(v[2]), "=&v"(v[3]), "=&v"(v[4]), "=&v"(v[5]),
+          "=&v"(v[6]), "=&v"(v[7]), "=&v"(v[8]), "=&v"(v[9]), "=&v"(v[10]), "=&v"(v[11])
+        : "v"(pa), "v"(pc), "v"(pe), "i"(kOff), "i"(kOff + 8), "i"(kOff + kRowBytes),
+          "i"(kOff + kRowBytes + 8)
+        : "memory");
+}
+
+// One patch row (4 pixel pairs) of S_1 and S_2.
+__device__ __forceinline__ void weighted_row(const uint32_t *wrow, uint64_t a0, uint64_t a1, uint64_t c0,
+                                             uint64_t c1, uint64_t e0, uint64_t e1, int &s1, int &s2)
+{
+    const uint32_t av[4] = {(uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)};
+    const uint32_t cv[4] = {(uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32)};
+    const uint32_t ev[4] = {(uint32_t)e0, (uint32_t)(e0 >> 32), (uint32_t)e1, (uint32_t)(e1 >> 32)};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const short2v wv = __builtin_bit_cast(short2v, wrow[i]);
+        const short2v A = __builtin_bit_cast(short2v, av[i]);
+        const short2v d1 = A - __builtin_bit_cast(short2v, cv[i]);
+        const short2v d2 = A - __builtin_bit_cast(short2v, ev[i]);
+        s1 = __builtin_amdgcn_sdot2(wv * d1, d1, s1, false);
+        s2 = __builtin_amdgcn_sdot2(wv * d2, d2, s2, false);
+    }
+}
+
+template <int kR, int kRowBytes>
+__device__ __forceinline__ void weighted_rows(uint32_t base, uint32_t oa, uint32_t o1, uint32_t o2,
+                                              const WeightRows &w, int &s1, int &s2)
+{
+    uint64_t v[12];
+    load_row_pair<kR * kRowBytes, kRowBytes>(base + oa, base + o1, base + o2, v);
+    weighted_row(w.pair + 4 * kR, v[0], v[1], v[2], v[3], v[4], v[5], s1, s2);
+    weighted_row(w.pair + 4 * (kR + 1), v[6], v[7], v[8], v[9], v[10], v[11], s1, s2);
+}
+
 // S_j of one triplet: patch rows at byte offsets off + r kRowBytes.
 template <int kW>
 __device__ __forceinline__ bool weighted_bit(const uint8_t *lds, uint32_t oa, uint32_t o1, uint32_t o2,
                                              const WeightRows &w)
 {
-    using G = WGeom<kW>;
+    constexpr int kRB = WGeom<kW>::kRowBytes;
+    const uint32_t base = (uint32_t)(uintptr_t)lds;
     int s1 = 0, s2 = 0;
-#pragma unroll
-    for (int r = 0; r < 8; ++r) {
-        // Patch rows start on quadwords (not 16-byte lines): two 8-byte reads.
-        const uint2 *pa = reinterpret_cast<const uint2 *>(lds + oa + r * G::kRowBytes);
-        const uint2 *pc = reinterpret_cast<const uint2 *>(lds + o1 + r * G::kRowBytes);
-        const uint2 *pe = reinterpret_cast<const uint2 *>(lds + o2 + r * G::kRowBytes);
-        const uint2 a0 = pa[0], a1 = pa[1], c0 = pc[0], c1 = pc[1], e0 = pe[0], e1 = pe[1];
-        const uint32_t av[4] = {a0.x, a0.y, a1.x, a1.y}, cv[4] = {c0.x, c0.y, c1.x, c1.y},
-                       ev[4] = {e0.x, e0.y, e1.x, e1.y};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const short2v wv = __builtin_bit_cast(short2v, w.pair[4 * r + i]);
-            const short2v A = __builtin_bit_cast(short2v, av[i]);
-            const short2v d1 = A - __builtin_bit_cast(short2v, cv[i]);
-            const short2v d2 = A - __builtin_bit_cast(short2v, ev[i]);
-            s1 = __builtin_amdgcn_sdot2(wv * d1, d1, s1, false);
-            s2 = __builtin_amdgcn_sdot2(wv * d2, d2, s2, false);
-        }
-    }
+    weighted_rows<0, kRB>(base, oa, o1, o2, w, s1, s2);
+    weighted_rows<2, kRB>(base, oa, o1, o2, w, s1, s2);
+    weighted_rows<4, kRB>(base, oa, o1, o2, w, s1, s2);
+    weighted_rows<6, kRB>(base, oa, o1, o2, w, s1, s2);
     return s1 > s2;
 }
 

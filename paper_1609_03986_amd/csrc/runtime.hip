@@ -542,7 +542,7 @@ int latch_create_geometry(latch_handle *out, const uint8_t *triplets_host, int w
     for (int w = 0; w < kWWaves; ++w)
         for (int i = 0; i < kWPerWave; ++i) mem[kWPerWave * w + i] = toff[member(w, i)];
     uint8_t slot_of[kTriplets];
-    assign_slots(mem, kWWaves, kWPerWave, 16, 16, slot_of);   // row reads: ds_read2_b64
+    assign_slots(mem, kWWaves, kWPerWave, 32, 32, slot_of);   // row reads: ds_read_b64
     uint2 toff_slot[kTriplets];
     uint32_t unperm[kWWaves * 64] = {};
     for (int w = 0; w < kWWaves; ++w)
