@@ -149,20 +149,24 @@ __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
 
 constexpr int kMTile = 16;                               // queries per side
 constexpr int kMaxRadius = 8;
-constexpr int kMRegion = kMTile + 2 * kMaxRadius;        // 32
+static_assert((kMTile + 2 * kMaxRadius) * (kMTile + 2 * kMaxRadius) * 64 <= 65536,
+              "the largest region fits the default dynamic LDS limit");
 
 __global__ __launch_bounds__(kDThreads) void dense_match_kernel(
     const uint32_t *__restrict__ query, const uint32_t *__restrict__ train, int gw, int gh, int radius,
     int tiles_x, int k, float ratio, int32_t *__restrict__ idx, int32_t *__restrict__ dist,
     uint8_t *__restrict__ accept)
 {
-    // Train descriptors of the region, 64 B each; the four 16-byte chunks of
-    // position p are stored at chunk (c ^ (p & 3)) so that neighbouring
-    // positions read by neighbouring lanes fall in distinct banks.
-    __shared__ uint4 region[kMRegion * kMRegion * 4];
+    // Train descriptors of the (16 + 2 radius)^2 region, 64 B each, stored
+    // chunk-major: the 16-byte chunk c of position p is region[c plane + p].
+    // The 16 lanes of a query row read chunk c of 16 consecutive positions,
+    // 256 contiguous bytes, which LDS serves without bank conflicts.  The
+    // launch sizes the region for the radius (36 KB at radius 4).
+    extern __shared__ uint4 region[];
     const int tx = (int)(blockIdx.x % (unsigned)tiles_x), ty = (int)(blockIdx.x / (unsigned)tiles_x);
     const int t = threadIdx.x;
     const int side = kMTile + 2 * radius;
+    const int plane = side * side;
     const int rx0 = tx * kMTile - radius, ry0 = ty * kMTile - radius;
     for (int i = t; i < side * side * 4; i += kDThreads) {
         const int p = i >> 2, c = i & 3;
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(kDThreads) void dense_match_kernel(
         uint4 val = make_uint4(0u, 0u, 0u, 0u);
         if (gy >= 0 && gy < gh && gx >= 0 && gx < gw)
             val = reinterpret_cast<const uint4 *>(train + ((size_t)gy * gw + gx) * kWords)[c];
-        region[4 * p + (c ^ (p & 3))] = val;
+        region[c * plane + p] = val;
     }
     const int qx = tx * kMTile + (t & 15), qy = ty * kMTile + (t >> 4);
     const bool real = qx < gw && qy < gh;
@@ -199,7 +203,7 @@ __global__ __launch_bounds__(kDThreads) void dense_match_kernel(
             uint32_t d = 0;
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
-                const uint4 w = region[4 * p + (c ^ (p & 3))];
+                const uint4 w = region[c * plane + p];
                 d += __builtin_popcount(w.x ^ qd[4 * c]) + __builtin_popcount(w.y ^ qd[4 * c + 1]) +
                      __builtin_popcount(w.z ^ qd[4 * c + 2]) + __builtin_popcount(w.w ^ qd[4 * c + 3]);
             }
@@ -258,7 +262,10 @@ hipError_t launch_dense_match(const DenseMatchArgs &a, hipStream_t stream)
 {
     const int tiles_x = (a.gw + kMTile - 1) / kMTile;
     const int64_t tiles = (int64_t)tiles_x * ((a.gh + kMTile - 1) / kMTile);
-    hipLaunchKernelGGL(dense_match_kernel, dim3((unsigned)tiles), dim3(kDThreads), 0, stream, a.query,
+    if (a.radius < 0 || a.radius > kMaxRadius) return hipErrorInvalidValue;
+    const int side = kMTile + 2 * a.radius;
+    const size_t lds = (size_t)side * side * 4 * sizeof(uint4);   // <= 64 KB
+    hipLaunchKernelGGL(dense_match_kernel, dim3((unsigned)tiles), dim3(kDThreads), lds, stream, a.query,
                        a.train, a.gw, a.gh, a.radius, tiles_x, a.k, a.ratio, a.idx, a.dist, a.accept);
     return hipGetLastError();
 }
