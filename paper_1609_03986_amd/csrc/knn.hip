@@ -171,6 +171,24 @@ __device__ __forceinline__ void store_pair(uint64_t b1, uint64_t b2, int nq, int
     }
 }
 
+// The 16 words of query row qn, zeros past nq, with every load issued
+// before any is used: one memory round trip per row.  (Loads guarded word by
+// word compile to a branch and a wait per word.)
+__device__ __forceinline__ void load_query_row(const uint32_t *__restrict__ query, int nq, int qn,
+                                               uint32_t (&w)[kWords])
+{
+    const bool real = qn < nq;
+#pragma unroll
+    for (int i = 0; i < kWords; ++i) w[i] = 0u;
+    if (nq > 0) {
+        const uint32_t *src = query + (size_t)(real ? qn : 0) * kWords;
+#pragma unroll
+        for (int i = 0; i < kWords; ++i) w[i] = src[i];
+    }
+#pragma unroll
+    for (int i = 0; i < kWords; ++i) w[i] = real ? w[i] : 0u;
+}
+
 // One work item of the MFMA matcher: queries qgroup * 256 .. + 255 of
 // `query` (nq rows) against train rows split * split_rows .. + split_rows - 1
 // of `train` (nt rows).  All 256 threads of the workgroup take part; tbuf is
@@ -199,13 +217,15 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
     // Resident query fragments and query popcounts.
     v4i bq[kQueryBlocks][16];
     int na[kQueryBlocks];
+    uint32_t qw[kQueryBlocks][kWords];
+#pragma unroll
+    for (int qb = 0; qb < kQueryBlocks; ++qb) load_query_row(query, nq, qbase + 32 * qb + (lane & 31), qw[qb]);
 #pragma unroll
     for (int qb = 0; qb < kQueryBlocks; ++qb) {
-        const int qn = qbase + 32 * qb + (lane & 31);
         int pc = 0;
 #pragma unroll
         for (int s = 0; s < 16; ++s) {
-            const uint32_t w = qn < nq ? query[(size_t)qn * kWords + s] : 0u;
+            const uint32_t w = qw[qb][s];
             pc += __popc(w);
             bq[qb][s] = expand16_pm1((w >> (16 * half)) & 0xffffu);
         }
@@ -421,14 +441,15 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     // Resident query fragments (+-1) and query popcounts.
     uint4 bq[QB][kFp4Steps];
     int na[QB];
+    uint32_t qw[QB][kWords];
+#pragma unroll
+    for (int qb = 0; qb < QB; ++qb) load_query_row(query, nq, qbase + 32 * qb + (lane & 31), qw[qb]);
 #pragma unroll
     for (int qb = 0; qb < QB; ++qb) {
-        const int qn = qbase + 32 * qb + (lane & 31);
         int pc = 0;
 #pragma unroll
         for (int s = 0; s < kFp4Steps; ++s) {
-            const uint32_t w0 = qn < nq ? query[(size_t)qn * kWords + 2 * s] : 0u;
-            const uint32_t w1 = qn < nq ? query[(size_t)qn * kWords + 2 * s + 1] : 0u;
+            const uint32_t w0 = qw[qb][2 * s], w1 = qw[qb][2 * s + 1];
             pc += __popc(w0) + __popc(w1);
             bq[qb][s] = fp4_word(half ? w1 : w0, lut_query);
         }
@@ -561,8 +582,7 @@ __device__ __forceinline__ void popcount_item(const uint32_t *__restrict__ query
     const int j1 = min(nt, j0 + split_rows);
 
     uint32_t q[kWords];
-#pragma unroll
-    for (int w = 0; w < kWords; ++w) q[w] = qn < nq ? query[(size_t)qn * kWords + w] : 0u;
+    load_query_row(query, nq, qn, q);
 
     uint32_t k1 = ~0u, k2 = ~0u;
 #pragma unroll 4
