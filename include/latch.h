@@ -226,8 +226,9 @@ int hamming_knn_window(latch_handle h, const uint32_t *query_dev, const uint32_t
  *               detection and extraction with no host round trip.
  *   image_id_dev: int32[max_kps] or NULL: if given, image_index is written
  *               for every keypoint written.
- * Uses the handle's workspace (8 * height * ceil(width / 64) + 8 * height
- * bytes, grown as needed); images below 33 x 33 have no keypoints.  Calls that share a
+ * Uses the handle's workspace (about 8 * height * ceil(width / 64) + 8 * height
+ * + height * ceil(ceil(width / 64) / 16) * 16 bytes, grown as needed); images
+ * below 33 x 33 have no keypoints.  Calls that share a
  * handle or a count must be ordered (one stream).
  */
 int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,

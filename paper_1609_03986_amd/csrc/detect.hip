@@ -132,7 +132,7 @@ constexpr int stage_lds_rows()
 template <bool kDword>
 __global__ __launch_bounds__(kThreads) void detect_tile_kernel(
     const uint8_t *__restrict__ img, int height, int width, int pitch, int threshold, int tiles_x,
-    uint64_t *__restrict__ masks)
+    uint64_t *__restrict__ masks, uint8_t *__restrict__ counts, int count_stride)
 {
     __shared__ __align__(16) uint8_t timg[stage_lds_rows<kImgH, kImgW>() * kImgW];
     __shared__ uint8_t tscore[kScoreH * kScoreW];
@@ -171,7 +171,10 @@ __global__ __launch_bounds__(kThreads) void detect_tile_kernel(
                           s > p[-1] && s > p[1] && s > p[kScoreW - 1] && s > p[kScoreW] &&
                           s > p[kScoreW + 1];
         const uint64_t m = __ballot(keep);
-        if (lane == 0) masks[(size_t)tx * height + y] = m;
+        if (lane == 0) {
+            masks[(size_t)tx * height + y] = m;
+            counts[(size_t)y * count_stride + tx] = (uint8_t)__popcll(m);
+        }
     }
 }
 
@@ -194,8 +197,8 @@ __device__ __forceinline__ int64_t block_inclusive_scan(int64_t v, int64_t *wave
 }
 
 __global__ __launch_bounds__(kScanThreads) void detect_scan_kernel(
-    const uint64_t *__restrict__ masks, int height, int tiles_x, int64_t *__restrict__ row_first,
-    int64_t *__restrict__ base_out, int64_t *__restrict__ n_kps)
+    const uint8_t *__restrict__ counts, int count_stride, int height, int tiles_x,
+    int64_t *__restrict__ row_first, int64_t *__restrict__ base_out, int64_t *__restrict__ n_kps)
 {
     __shared__ int64_t wave_tot[kScanThreads / 64];
     __shared__ int64_t base, chunk_total;
@@ -205,23 +208,49 @@ __global__ __launch_bounds__(kScanThreads) void detect_scan_kernel(
         *base_out = base;
     }
     __syncthreads();
-    int64_t carry = base;
-    for (int r0 = 0; r0 < height; r0 += kScanThreads) {
-        const int r = r0 + threadIdx.x;
+    const int chunks = count_stride / 16;                 // 16 tile counts per chunk
+    // Survivors of row r: its counts, one byte per tile, four 16-byte chunks
+    // in flight; bytes past tiles_x (never written) are masked off.
+    auto row_count = [&](const uint4 (&v)[4], int i) {
         int64_t c = 0;
-        if (r < height) {
-            // The row's masks (tile-major, so consecutive rows are adjacent
-            // and every load of the workgroup is coalesced), 16 in flight.
-            for (int i = 0; i < tiles_x; i += 16) {
-                uint64_t m[16];
 #pragma unroll
-                for (int k = 0; k < 16; ++k) m[k] = masks[(size_t)min(i + k, tiles_x - 1) * height + r];
+        for (int k = 0; k < 4; ++k) {
+            const int valid = min(max(tiles_x - 16 * (i + k), 0), 16);
+            const uint32_t w[4] = {v[k].x, v[k].y, v[k].z, v[k].w};
 #pragma unroll
-                for (int k = 0; k < 16; ++k) c += i + k < tiles_x ? __popcll(m[k]) : 0;
+            for (int d = 0; d < 4; ++d) {
+                const int nb = min(max(valid - 4 * d, 0), 4);
+                const uint32_t keep = nb == 4 ? 0xffffffffu : (1u << (8 * nb)) - 1u;
+                c += __builtin_amdgcn_sad_u8(w[d] & keep, 0u, 0u);
             }
         }
+        return c;
+    };
+    int64_t carry = base;
+    // Two rows per thread, so one pass covers 2048 rows.
+    for (int r0 = 0; r0 < height; r0 += 2 * kScanThreads) {
+        const int r = r0 + 2 * (int)threadIdx.x;
+        int64_t c0 = 0, c1 = 0;
+        if (r < height) {
+            const uint4 *row0 = reinterpret_cast<const uint4 *>(counts + (size_t)r * count_stride);
+            const uint4 *row1 =
+                reinterpret_cast<const uint4 *>(counts + (size_t)min(r + 1, height - 1) * count_stride);
+            for (int i = 0; i < chunks; i += 4) {
+                uint4 v0[4], v1[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    v0[k] = row0[min(i + k, chunks - 1)];
+                    v1[k] = row1[min(i + k, chunks - 1)];
+                }
+                c0 += row_count(v0, i);
+                c1 += row_count(v1, i);
+            }
+            if (r + 1 >= height) c1 = 0;
+        }
+        const int64_t c = c0 + c1;
         const int64_t incl = block_inclusive_scan(c, wave_tot);
         if (r < height) row_first[r] = carry + incl - c;
+        if (r + 1 < height) row_first[r + 1] = carry + incl - c1;
         if (threadIdx.x == kScanThreads - 1) chunk_total = incl;
         __syncthreads();
         carry += chunk_total;
@@ -412,11 +441,11 @@ hipError_t launch_detect(const DetectArgs &a, hipStream_t stream)
                        (a.width & 3) == 0;
     hipLaunchKernelGGL(dword ? detect_tile_kernel<true> : detect_tile_kernel<false>,
                        dim3((unsigned)tiles), dim3(kThreads), 0, stream, a.img, a.height, a.width,
-                       a.pitch, a.threshold, tiles_x, a.masks);
+                       a.pitch, a.threshold, tiles_x, a.masks, a.counts, a.count_stride);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, a.masks, a.height,
-                       tiles_x, a.row_first, a.base, a.n_kps);
+    hipLaunchKernelGGL(detect_scan_kernel, dim3(1), dim3(kScanThreads), 0, stream, a.counts,
+                       a.count_stride, a.height, tiles_x, a.row_first, a.base, a.n_kps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(dword ? detect_emit_kernel<true> : detect_emit_kernel<false>,
                        dim3((unsigned)tiles), dim3(kThreads), 0, stream, a.img, a.height, a.width,

@@ -125,6 +125,8 @@ struct DetectArgs {
     const uint8_t *img;
     int height, width, pitch, threshold;
     uint64_t *masks;          // workspace: survivor mask per (row, 64-column tile)
+    uint8_t *counts;          // workspace: survivors per (row, tile), rows of count_stride bytes
+    int count_stride;         // bytes per counts row: tiles rounded up to a multiple of 16
     int64_t *row_first;       // workspace: height (absolute output slot of each row)
     int64_t *base;            // workspace: the count on entry
     float4 *kps;

@@ -721,7 +721,9 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
         return fail(h, LATCH_EINVAL, "max_kps = %lld", (long long)max_kps);
     const size_t mask_bytes = align_up((size_t)height * ((width + 63) / 64) * sizeof(uint64_t), 256);
     const size_t first_bytes = align_up((size_t)height * sizeof(int64_t), 256);
-    const int rc = ensure_workspace(h, mask_bytes + first_bytes + sizeof(int64_t));
+    const int count_stride = (int)align_up((size_t)(width + 63) / 64, 16);
+    const size_t count_bytes = align_up((size_t)height * count_stride, 256);
+    const int rc = ensure_workspace(h, mask_bytes + first_bytes + count_bytes + sizeof(int64_t));
     if (rc != LATCH_OK) return rc;
     DetectArgs a;
     a.img = img_dev;
@@ -731,7 +733,9 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
     a.threshold = threshold;
     a.masks = reinterpret_cast<uint64_t *>(h->ws);
     a.row_first = reinterpret_cast<int64_t *>(h->ws + mask_bytes);
-    a.base = reinterpret_cast<int64_t *>(h->ws + mask_bytes + first_bytes);
+    a.counts = h->ws + mask_bytes + first_bytes;
+    a.count_stride = count_stride;
+    a.base = reinterpret_cast<int64_t *>(h->ws + mask_bytes + first_bytes + count_bytes);
     a.kps = reinterpret_cast<float4 *>(kps_dev);
     a.max_kps = max_kps;
     a.n_kps = n_kps_dev;
