@@ -343,8 +343,9 @@ __device__ __forceinline__ int orientation_bin(int m10, int m01)
 template <bool kDword>
 __global__ __launch_bounds__(kThreads) void detect_emit_kernel(
     const uint8_t *__restrict__ img, int height, int width, int pitch, int tiles_x,
-    const uint64_t *__restrict__ masks, const int64_t *__restrict__ row_first,
-    float4 *__restrict__ kps, int64_t max_kps, int32_t *__restrict__ image_id, int32_t image_index)
+    const uint64_t *__restrict__ masks, const uint8_t *__restrict__ counts, int count_stride,
+    const int64_t *__restrict__ row_first, float4 *__restrict__ kps, int64_t max_kps,
+    int32_t *__restrict__ image_id, int32_t image_index)
 {
     // Rows past kOriRows take the rounding of the load count (never read).
     __shared__ __align__(16) uint8_t win[stage_lds_rows<kOriRows, kOriCols>() * kOriStride];
@@ -380,9 +381,10 @@ __global__ __launch_bounds__(kThreads) void detect_emit_kernel(
         if (y >= height) break;                           // uniform across the wavefront
         uint64_t m = masks[(size_t)tx * height + y];
         const int64_t rf = row_first[y];
-        // Survivors of the tiles to the left in this row (one tile per lane).
-        int64_t left = 0;
-        for (int i = lane; i < tx; i += 64) left += __popcll(masks[(size_t)i * height + y]);
+        // Survivors of the tiles to the left in this row: their count bytes,
+        // one tile per lane (one coalesced load for up to 64 tiles).
+        int left = 0;
+        for (int i = lane; i < tx; i += 64) left += counts[(size_t)y * count_stride + i];
         if (m == 0) continue;
 #pragma unroll
         for (int o = 32; o > 0; o >>= 1) left += __shfl_xor(left, o);
@@ -449,8 +451,8 @@ hipError_t launch_detect(const DetectArgs &a, hipStream_t stream)
     if ((e = hipGetLastError()) != hipSuccess) return e;
     hipLaunchKernelGGL(dword ? detect_emit_kernel<true> : detect_emit_kernel<false>,
                        dim3((unsigned)tiles), dim3(kThreads), 0, stream, a.img, a.height, a.width,
-                       a.pitch, tiles_x, a.masks, a.row_first, a.kps, a.max_kps, a.image_id,
-                       a.image_index);
+                       a.pitch, tiles_x, a.masks, a.counts, a.count_stride, a.row_first, a.kps,
+                       a.max_kps, a.image_id, a.image_index);
     return hipGetLastError();
 }
 
