@@ -22,13 +22,16 @@
 //   1. detect_tile_kernel: a 64 x 16 tile per workgroup.  The image tile with
 //      a 4-pixel halo is staged in LDS, scores of the tile and a 1-pixel halo
 //      go to LDS, and each wavefront's ballot over one tile row is that row's
-//      64-bit survivor mask (written to the workspace).
-//   2. detect_scan_kernel: one workgroup turns the masks' per-row popcounts
-//      into each row's first output slot, and the new total.
+//      64-bit survivor mask; the mask and its popcount (one byte per row and
+//      tile, rows of the count array padded to 16 bytes) go to the workspace.
+//   2. detect_scan_kernel: one workgroup sums each row's count bytes (two
+//      rows per thread) and scans them into each row's first output slot and
+//      the new total.
 //   3. detect_emit_kernel: per tile, the image window of every disc staged in
-//      LDS; per tile row, the slot of each survivor from the row's first slot
-//      and the masks to its left, its orientation with one disc row per lane
-//      (two keypoints per wavefront), then the keypoint written once, complete.
+//      LDS; per tile row, the slot of each survivor from the row's first slot,
+//      the count bytes of the tiles to its left and the mask, its orientation
+//      with one disc row per lane (two keypoints per wavefront), then the
+//      keypoint written once, complete.
 #include "internal.h"
 
 namespace latch {
