@@ -58,6 +58,20 @@ def test_textured_image_all_bins(torch_cuda, lat):
     assert len(np.unique(want[:, 2])) > 1000
 
 
+@pytest.mark.parametrize("shape", [(40, 4500), (300, 4160), (2200, 160)])
+def test_wide_and_tall_images(torch_cuda, lat, shape):
+    """Rows of more than 64 tiles (several count chunks per row, the emit
+    kernel's left sum over two lane passes, a partial last chunk) and more than
+    2048 rows (a second scan pass carrying the running total)."""
+    g = np.random.default_rng(shape[0] + 7 * shape[1])
+    img = synth.textured_image(g, *shape)
+    want, wn = oracle.detect(img, 20)
+    kps, n = run(torch_cuda, lat, img, 20, max(wn, 1))
+    print(shape, wn)
+    assert n == wn and wn > 0
+    assert np.array_equal(kps[:n], want)
+
+
 def test_truncation_keeps_raster_prefix_and_full_count(torch_cuda, lat):
     g = np.random.default_rng(3)
     img = synth.smoothed_noise(g, 300, 400)
