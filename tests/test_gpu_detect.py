@@ -176,3 +176,28 @@ def test_append_past_capacity(torch_cuda, lat):
     assert int(n.item()) == 2 * na + nb
     K = kps.cpu().numpy()
     assert np.array_equal(K[:na], ka) and np.array_equal(K[na:], kb[:cap - na])
+
+
+def dot_image(shape, pts, background=30):
+    img = np.full(shape, background, np.uint8)
+    for x, y, v in pts:
+        img[y, x] = v
+    return img
+
+
+@pytest.mark.parametrize("shape,pts", [
+    ((64, 70), [(33, 40, 230), (34, 40, 230)]),                  # equal plateau: none kept
+    ((64, 70), [(33, 40, 230), (34, 41, 200)]),                  # diagonal, weaker dropped
+    ((64, 70), [(33, 40, 230), (32, 41, 230)]),                  # equal diagonal: none kept
+    ((64, 70), [(33, 40, 230), (35, 40, 200)]),                  # two apart: both kept
+    ((64, 70), [(16, 24, 230), (15, 44, 230), (53, 30, 230), (54, 50, 230)]),   # left/right border
+    ((64, 70), [(24, 16, 230), (44, 15, 230), (30, 47, 230), (50, 48, 230)]),   # top/bottom border
+    ((33, 33), [(16, 16, 230)]),
+    ((32, 32), [(16, 16, 230)]),
+])
+def test_suppression_and_border_cases(torch_cuda, lat, shape, pts):
+    img = dot_image(shape, pts)
+    want, wn = oracle.detect(img, 10)
+    kps, n = run(torch_cuda, lat, img, 10, 8)
+    assert n == wn
+    assert np.array_equal(kps[:n], want)

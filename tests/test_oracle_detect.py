@@ -159,3 +159,127 @@ def test_orientation_bin_does_not_depend_on_last_bits_of_atan2():
     err = 4 * 2.0 ** -51 * float(C) + 2 * 2048 * 2.0 ** -53
     assert M < 1 << 21
     assert worst > 2 * err, (float(worst), err)
+
+
+# --- Suppression and border (the rule of the detector, fixed by this build:
+# keep a corner whose score is strictly above every corner among its 8
+# neighbours, and test only pixels at least 16 from every edge). ---
+
+def numpy_scores(img):
+    """FAST-9 score of every pixel whose circle fits, from the lattice circle:
+    per pixel, the largest over the 16 arcs of 9 and both polarities of the
+    smallest difference on the arc.  Pixels whose circle leaves the image get
+    -256 (never a corner)."""
+    h, w = img.shape
+    a = img.astype(np.int32)
+    ring = np.stack([np.roll(np.roll(a, -dy, 0), -dx, 1) for dx, dy in circle_offsets()])
+    best = np.full((h, w), -256, np.int32)
+    for sign in (1, -1):
+        d = sign * (ring - a[None])
+        for k in range(16):
+            arc = d[[(k + j) % 16 for j in range(9)]].min(axis=0)
+            best = np.maximum(best, arc)
+    best[:3, :] = best[-3:, :] = -256
+    best[:, :3] = best[:, -3:] = -256
+    return best
+
+
+def numpy_detect_positions(img, t, border=16):
+    """Raster-ordered (x, y) of the corners that survive strict 8-neighbour
+    suppression, brute force."""
+    h, w = img.shape
+    s = numpy_scores(img)
+    S = np.zeros((h, w), np.int64)
+    inside = np.zeros((h, w), bool)
+    inside[border:h - border, border:w - border] = True
+    S[inside & (s > t)] = s[inside & (s > t)]
+    out = []
+    for y in range(h):
+        for x in range(w):
+            if S[y, x] <= 0:
+                continue
+            nb = [S[y + dy, x + dx] for dy in (-1, 0, 1) for dx in (-1, 0, 1)
+                  if (dx or dy) and 0 <= y + dy < h and 0 <= x + dx < w]
+            if all(S[y, x] > v for v in nb):
+                out.append((x, y))
+    return out
+
+
+def positions(kps):
+    return [(int(x), int(y)) for x, y, _, _ in kps]
+
+
+@pytest.mark.parametrize("shape,t,seed", [((48, 60), 10, 1), ((64, 70), 20, 2), ((33, 33), 5, 3),
+                                          ((40, 90), 15, 4), ((70, 41), 0, 5)])
+def test_detect_equals_brute_force_suppression(shape, t, seed):
+    g = np.random.default_rng(seed)
+    img = g.integers(0, 256, shape).astype(np.uint8) if seed % 2 else synth.smoothed_noise(g, *shape)
+    kps, n = oracle.detect(img, t)
+    want = numpy_detect_positions(img, t)
+    assert n == len(want) and positions(kps) == want
+
+
+def dots(shape, pts, background=30):
+    img = np.full(shape, background, np.uint8)
+    for x, y, v in pts:
+        img[y, x] = v
+    return img
+
+
+def test_equal_adjacent_corners_suppress_each_other():
+    # Two bright dots side by side: each has score 200, and neither lies on
+    # the other's circle, so the plateau keeps neither.
+    img = dots((64, 70), [(33, 40, 230), (34, 40, 230)])
+    assert oracle.fast_score(img, 33, 40) == 200 and oracle.fast_score(img, 34, 40) == 200
+    assert oracle.detect(img, 10)[1] == 0
+    # The same vertically.
+    assert oracle.detect(dots((64, 70), [(33, 40, 230), (33, 41, 230)]), 10)[1] == 0
+
+
+def test_corner_beside_a_stronger_one_is_dropped():
+    img = dots((64, 70), [(33, 40, 230), (34, 40, 200)])     # scores 200 and 170
+    kps, n = oracle.detect(img, 10)
+    assert n == 1 and positions(kps) == [(33, 40)]
+    img = dots((64, 70), [(33, 40, 180), (33, 41, 230)])
+    kps, n = oracle.detect(img, 10)
+    assert n == 1 and positions(kps) == [(33, 41)]
+
+
+@pytest.mark.parametrize("d", [(1, 1), (-1, 1), (1, -1), (-1, -1)])
+def test_diagonal_neighbours_take_part_in_suppression(d):
+    # A 4-neighbourhood would keep both dots.
+    x, y = 33, 40
+    img = dots((64, 70), [(x, y, 230), (x + d[0], y + d[1], 200)])
+    kps, n = oracle.detect(img, 10)
+    assert n == 1 and positions(kps) == [(x, y)]
+    img = dots((64, 70), [(x, y, 230), (x + d[0], y + d[1], 230)])
+    assert oracle.detect(img, 10)[1] == 0
+
+
+def test_two_pixels_apart_both_survive():
+    img = dots((64, 70), [(33, 40, 230), (35, 40, 200)])
+    kps, n = oracle.detect(img, 10)
+    assert n == 2 and positions(kps) == [(33, 40), (35, 40)]
+
+
+@pytest.mark.parametrize("h,w", [(64, 70), (50, 41)])
+def test_border_of_sixteen_pixels(h, w):
+    # A dot is kept iff it is at least 16 pixels from every edge: columns
+    # 16 .. w - 17 and rows 16 .. h - 17.
+    cases = [((16, 24), True), ((15, 24), False), ((w - 17, 24), True), ((w - 16, 24), False),
+             ((20, 16), True), ((20, 15), False), ((20, h - 17), True), ((20, h - 16), False)]
+    for (x, y), kept in cases:
+        kps, n = oracle.detect(dots((h, w), [(x, y, 230)]), 10)
+        assert n == (1 if kept else 0), (x, y)
+        if kept:
+            assert positions(kps) == [(x, y)]
+
+
+def test_smallest_images():
+    # 33 x 33 has exactly one pixel 16 from every edge; 32 x 32 has none.
+    kps, n = oracle.detect(dots((33, 33), [(16, 16, 230)]), 10)
+    assert n == 1 and positions(kps) == [(16, 16)]
+    assert oracle.detect(dots((32, 32), [(16, 16, 230)]), 10)[1] == 0
+    assert oracle.detect(dots((32, 32), [(15, 15, 230)]), 10)[1] == 0
+    for h, w in [(33, 32), (32, 33), (1, 1), (16, 200)]:
+        assert oracle.detect(np.full((h, w), 77, np.uint8), 0)[1] == 0
