@@ -14,11 +14,23 @@
  *   - All buffers named *_dev are device pointers owned by the caller; the
  *     library never frees or retains them past the call's stream work.
  *   - Every call that takes a stream only enqueues work on that stream and
- *     returns; results are ready when the stream reaches that point.  No call
- *     synchronises the stream except latch_check_errors, latch_timing_read,
- *     latch_destroy and a hamming_knn call that has to grow the workspace.
+ *     returns; results are ready when the stream reaches that point.  The
+ *     work calls (extraction, detection, matching, plan runs) never allocate,
+ *     free or synchronise.  The calls that wait, and for what:
+ *       latch_create, latch_create_geometry: their own table uploads, on a
+ *         private stream (nothing the caller enqueued);
+ *       latch_reserve: the whole device, only when it replaces a smaller
+ *         workspace (work on any stream may still use the old one);
+ *       latch_plan_create: its own capture stream (no device work runs);
+ *       latch_check_errors: the given stream;
+ *       latch_timing_enable, latch_timing_read: the recorded events;
+ *       latch_destroy, latch_plan_destroy: the whole device.
  *   - A handle owns device copies of the rotation table and triplet table,
- *     a sticky error word and a grow-only workspace.  A handle is not
+ *     a sticky error word and a workspace that only latch_reserve sizes.
+ *     hamming_knn (with more than one train split), hamming_knn_batch and
+ *     latch_detect need workspace; the *_workspace_size calls give the bytes
+ *     for given sizes, and a call whose need exceeds what the handle holds
+ *     returns LATCH_EWORKSPACE and enqueues nothing.  A handle is not
  *     thread-safe, and work enqueued through one handle on different streams
  *     shares its workspace: order such calls yourself or use one handle per
  *     stream.
@@ -72,7 +84,9 @@ typedef enum {
     LATCH_EINVAL = -1,   /* bad argument (null pointer, negative or too large size, ...) */
     LATCH_ENOMEM = -2,   /* device allocation failed */
     LATCH_EDEVICE = -3,  /* a HIP runtime call failed */
-    LATCH_ERANGE = -4    /* a value outside its documented range (triplet centre, k, ratio) */
+    LATCH_ERANGE = -4,   /* a value outside its documented range (triplet centre, k, ratio) */
+    LATCH_EWORKSPACE = -5  /* the handle's workspace is smaller than the call needs: reserve
+                              the size the matching *_workspace_size call gives, then retry */
 } latch_status;
 
 typedef enum {
@@ -133,6 +147,41 @@ int latch_create_geometry(latch_handle *h, const uint8_t *triplets_host, int win
 
 /* Release a handle and its device memory (synchronises the device first).  NULL is a no-op. */
 void latch_destroy(latch_handle h);
+
+/*
+ * Workspace sizes (host arithmetic only: no GPU work, no synchronisation).
+ * *bytes receives the device workspace the call with these arguments needs
+ * on this handle, 0 when it needs none.
+ *   hamming_knn_workspace_size: the train rows are split over workgroups
+ *     (Sec. 4 streams the gallery through the matcher in parts); with more
+ *     than one split, 16 bytes per (query, split) of partial top-2 keys.
+ *     The split count depends on nq, nt, the path (LATCH_PATH_AUTO resolved
+ *     by the handle's current tuning table) and the tuning's workgroup
+ *     targets, so query after latch_set_tuning.
+ *   hamming_knn_batch_workspace_size: the pair table's per-pair state and
+ *     the work-item list of the persistent matcher.
+ *   latch_detect_workspace_size: survivor masks, counts and row offsets of
+ *     an image of height x width.
+ * LATCH_EINVAL for a NULL pointer or sizes outside the limits of the call.
+ */
+int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path, size_t *bytes);
+int hamming_knn_batch_workspace_size(latch_handle h, int n_pairs, int64_t out_rows, size_t *bytes);
+int latch_detect_workspace_size(latch_handle h, int height, int width, size_t *bytes);
+
+/*
+ * Make the handle's workspace at least `bytes` (a set-up call, made before
+ * the work calls that need it, e.g. once per serving slot for its largest
+ * request, or before capturing a graph).  A handle that holds at least
+ * `bytes` is left as it is.  Otherwise a new buffer of `bytes` (rounded up
+ * to 256) is allocated with hipMalloc; when a smaller one exists, the call
+ * first waits for the whole device and frees it.  *held_out (may be NULL)
+ * receives the size now held, so latch_reserve(h, 0, &held) only reports.
+ * LATCH_ENOMEM if the allocation fails (the handle then holds no workspace).
+ * A HIP graph captured from calls that use the workspace holds its address:
+ * reserve enough before capturing, since a later reservation that replaces
+ * the buffer invalidates such graphs.
+ */
+int latch_reserve(latch_handle h, size_t bytes, size_t *held_out);
 
 /*
  * Extract LATCH descriptors (Sec. 3.1 Eq. 1; window resampling per rule 1-5 above).
@@ -226,10 +275,11 @@ int hamming_knn_window(latch_handle h, const uint32_t *query_dev, const uint32_t
  *               detection and extraction with no host round trip.
  *   image_id_dev: int32[max_kps] or NULL: if given, image_index is written
  *               for every keypoint written.
- * Uses the handle's workspace (about 8 * height * ceil(width / 64) + 8 * height
- * + height * ceil(ceil(width / 64) / 16) * 16 bytes, grown as needed); images
- * below 33 x 33 have no keypoints.  Calls that share a
- * handle or a count must be ordered (one stream).
+ * Uses the handle's workspace (latch_detect_workspace_size: about
+ * 8 * height * ceil(width / 64) + 8 * height + 16 * height * ceil(ceil(width / 64) / 16)
+ * bytes; LATCH_EWORKSPACE if the handle holds less); images below 33 x 33
+ * have no keypoints.  Calls that share a handle or a count must be ordered
+ * (one stream).
  */
 int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, int pitch,
                  int threshold, latch_keypoint *kps_dev, int64_t max_kps, int64_t *n_kps_dev,
@@ -248,10 +298,10 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
  *              exactly (the second neighbour is always searched, also for k = 1).
  *   path:      a latch_path value; every path returns identical results.
  * nq == 0 is a no-op.  nq and nt must be < 2^31.  The train rows are split
- * over workgroups; with more than one split a merge kernel follows.  May
- * grow the handle's workspace (a device allocation, LATCH_ENOMEM on
- * failure); calls on one handle must not overlap in time on different
- * streams.
+ * over workgroups; with more than one split a merge kernel follows and the
+ * partials live in the handle's workspace (hamming_knn_workspace_size;
+ * LATCH_EWORKSPACE if the handle holds less).  Calls on one handle must not
+ * overlap in time on different streams.
  */
 int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
                 const uint32_t *train_dev, int64_t nt, int k, float ratio,
@@ -281,7 +331,9 @@ typedef struct {
  * A pair whose ranges fall outside query_rows / train_rows / out_rows, or
  * with nt > 2^21 - 32, is skipped and sets LATCH_FLAG_BAD_PAIR.  Pairs'
  * output ranges should not overlap (they are written concurrently).  k,
- * ratio and path as for hamming_knn.  May grow the handle's workspace.
+ * ratio and path as for hamming_knn.  Uses the handle's workspace
+ * (hamming_knn_batch_workspace_size; LATCH_EWORKSPACE if the handle holds
+ * less).
  */
 int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_rows,
                       const uint32_t *train_dev, int64_t train_rows, const latch_pair *pairs_dev,
@@ -290,12 +342,17 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
 
 /*
  * Plans: one batched extract + match sequence captured once as a HIP graph
- * and replayed with a single graph launch.  The plan fixes the device
- * buffers below (pointers), not their contents: between runs the caller may
- * rewrite the image table, keypoints, image ids, keypoint count and pairs.
- * Each run extracts descriptors for the batch's keypoints into `desc` (as
- * latch_extract_batch) and then matches the pairs, whose query and train
- * rows both index `desc` (as hamming_knn_batch).
+ * and replayed with a single graph launch.  The paper describes and then
+ * matches many images of a scene for structure from motion, where matching
+ * dominates the run time (Sec. 5, Table 2), and overlaps the images' work on
+ * streams (Sec. 4, "CUDA Integration"); a plan runs a whole batch of uneven
+ * images and image pairs as two persistent launches instead.  The plan fixes
+ * the device buffers below (pointers), not their contents: between runs the
+ * caller may rewrite the image table, keypoints, image ids, keypoint count
+ * and pairs.  Each run extracts descriptors for the batch's keypoints into
+ * `desc` (as latch_extract_batch) and then matches the pairs, whose query and
+ * train rows both index `desc` (as hamming_knn_batch).  The plan owns its
+ * matching workspace, so the handle's is not used.
  */
 typedef struct latch_plan_ctx *latch_plan;
 

@@ -10,6 +10,7 @@ The functions keep the C names:
     latch_destroy(handle)
     latch_extract(handle, img, kps, desc=None, stream=None) -> desc
     hamming_knn(handle, query, train, k=2, ratio=0.8, path="auto", ...) -> (idx, dist, accept)
+    hamming_knn_workspace_size(handle, nq, nt, path) -> bytes; latch_reserve(handle, bytes)
     latch_check_errors(handle, stream=None, clear=True) -> flags
     latch_rotation_table() -> (cos_q14, sin_q14)   (host only)
 """
@@ -21,17 +22,19 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblatch.so")
 
-LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE = 0, -1, -2, -3, -4
+LATCH_OK, LATCH_EINVAL, LATCH_ENOMEM, LATCH_EDEVICE, LATCH_ERANGE, LATCH_EWORKSPACE = 0, -1, -2, -3, -4, -5
 PATHS = {"auto": 0, "mfma": 1, "popcount": 2, "fp4": 3}
 FLAG_BAD_KEYPOINT = 1
 FLAG_BAD_IMAGE = 2
 FLAG_BAD_PAIR = 4
 NO_NEIGHBOUR_DIST = 513
 STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATCH_EDEVICE",
-                -4: "LATCH_ERANGE"}
+                -4: "LATCH_ERANGE", -5: "LATCH_EWORKSPACE"}
 
 # Every symbol include/latch.h declares.
-EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "latch_extract", "latch_extract_batch",
+EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "hamming_knn_workspace_size",
+           "hamming_knn_batch_workspace_size", "latch_detect_workspace_size", "latch_reserve",
+           "latch_extract", "latch_extract_batch",
            "latch_extract_dense", "hamming_knn_window", "latch_detect",
            "hamming_knn",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
@@ -72,6 +75,15 @@ def load_library():
     lib.latch_create_geometry.restype = I
     lib.latch_destroy.argtypes = [P]
     lib.latch_destroy.restype = None
+    SZ = ctypes.POINTER(ctypes.c_size_t)
+    lib.hamming_knn_workspace_size.argtypes = [P, I64, I64, I, SZ]
+    lib.hamming_knn_workspace_size.restype = I
+    lib.hamming_knn_batch_workspace_size.argtypes = [P, I, I64, SZ]
+    lib.hamming_knn_batch_workspace_size.restype = I
+    lib.latch_detect_workspace_size.argtypes = [P, I, I, SZ]
+    lib.latch_detect_workspace_size.restype = I
+    lib.latch_reserve.argtypes = [P, ctypes.c_size_t, SZ]
+    lib.latch_reserve.restype = I
     lib.latch_extract.argtypes = [P, P, I, I, I, P, I64, P, P]
     lib.latch_extract.restype = I
     lib.latch_extract_batch.argtypes = [P, P, I, P, P, I64, P, P, P]
@@ -117,6 +129,44 @@ def _check(h, rc):
     if rc != LATCH_OK:
         msg = load_library().latch_last_error(h)
         raise LatchError(rc, msg.decode() if msg else "")
+
+
+def _with_workspace(h, call, size):
+    """Run `call()`; if the handle's workspace is too small (the call then
+    enqueued nothing), reserve what `size()` reports and run it again.  The
+    reserve is the explicit set-up call of the C ABI (it waits for the device
+    only when it replaces a smaller workspace)."""
+    rc = call()
+    if rc == LATCH_EWORKSPACE:
+        latch_reserve(h, size())
+        rc = call()
+    _check(h, rc)
+
+
+def _size_out(h, fn, *args):
+    out = ctypes.c_size_t()
+    _check(h, fn(h, *args, ctypes.byref(out)))
+    return out.value
+
+
+def hamming_knn_workspace_size(h, nq, nt, path="auto"):
+    """Workspace bytes hamming_knn needs for these sizes on this handle."""
+    return _size_out(h, load_library().hamming_knn_workspace_size, int(nq), int(nt), PATHS[path])
+
+
+def hamming_knn_batch_workspace_size(h, n_pairs, out_rows):
+    return _size_out(h, load_library().hamming_knn_batch_workspace_size, int(n_pairs), int(out_rows))
+
+
+def latch_detect_workspace_size(h, height, width):
+    return _size_out(h, load_library().latch_detect_workspace_size, int(height), int(width))
+
+
+def latch_reserve(h, nbytes=0):
+    """Make the handle's workspace at least nbytes; returns the bytes it holds."""
+    held = ctypes.c_size_t()
+    _check(h, load_library().latch_reserve(h, int(nbytes), ctypes.byref(held)))
+    return held.value
 
 
 def _stream_ptr(stream):
@@ -254,11 +304,11 @@ def latch_detect(h, img, threshold, max_kps, kps=None, n_kps=None, image_id=None
         n_kps = torch.zeros((1,), dtype=torch.int64, device=dev)
     H, W = img.shape
     idp = _dev(image_id, torch.int32, "image_id") if image_id is not None else None
-    rc = load_library().latch_detect(h, _dev(img, torch.uint8, "img"), H, W, img.stride(0),
-                                     int(threshold), _dev(kps, torch.float32, "kps"), int(max_kps),
-                                     _dev(n_kps, torch.int64, "n_kps"), idp, int(image_index),
-                                     _stream_ptr(stream))
-    _check(h, rc)
+    args = (h, _dev(img, torch.uint8, "img"), H, W, img.stride(0), int(threshold),
+            _dev(kps, torch.float32, "kps"), int(max_kps), _dev(n_kps, torch.int64, "n_kps"), idp,
+            int(image_index), _stream_ptr(stream))
+    _with_workspace(h, lambda: load_library().latch_detect(*args),
+                    lambda: latch_detect_workspace_size(h, H, W))
     return kps, n_kps
 
 
@@ -314,11 +364,11 @@ def hamming_knn(h, query, train, k=2, ratio=0.8, path="auto", idx=None, dist=Non
         accept = torch.empty((nq,), dtype=torch.uint8, device=dev)
     acc_ptr = _dev(accept, torch.uint8, "accept") if accept is not None else None
     tptr = _dev(train, torch.int32, "train") if nt > 0 else None
-    rc = load_library().hamming_knn(h, _dev(query, torch.int32, "query"), nq, tptr, nt, int(k),
-                                    float(ratio), _dev(idx, torch.int32, "idx"),
-                                    _dev(dist, torch.int32, "dist"), acc_ptr, PATHS[path],
-                                    _stream_ptr(stream))
-    _check(h, rc)
+    args = (h, _dev(query, torch.int32, "query"), nq, tptr, nt, int(k), float(ratio),
+            _dev(idx, torch.int32, "idx"), _dev(dist, torch.int32, "dist"), acc_ptr, PATHS[path],
+            _stream_ptr(stream))
+    _with_workspace(h, lambda: load_library().hamming_knn(*args),
+                    lambda: hamming_knn_workspace_size(h, nq, nt, path))
     return idx, dist, accept
 
 
@@ -345,12 +395,11 @@ def hamming_knn_batch(h, query, train, pairs, out_rows, k=2, ratio=0.8, path="au
     acc_ptr = _dev(accept, torch.uint8, "accept") if accept is not None else None
     qptr = _dev(query, torch.int32, "query") if query.shape[0] else None
     tptr = _dev(train, torch.int32, "train") if train.shape[0] else None
-    rc = load_library().hamming_knn_batch(h, qptr, query.shape[0], tptr, train.shape[0],
-                                          _dev(pairs, torch.int64, "pairs"), pairs.shape[0],
-                                          int(k), float(ratio), _dev(idx, torch.int32, "idx"),
-                                          _dev(dist, torch.int32, "dist"), acc_ptr, int(out_rows),
-                                          PATHS[path], _stream_ptr(stream))
-    _check(h, rc)
+    args = (h, qptr, query.shape[0], tptr, train.shape[0], _dev(pairs, torch.int64, "pairs"),
+            pairs.shape[0], int(k), float(ratio), _dev(idx, torch.int32, "idx"),
+            _dev(dist, torch.int32, "dist"), acc_ptr, int(out_rows), PATHS[path], _stream_ptr(stream))
+    _with_workspace(h, lambda: load_library().hamming_knn_batch(*args),
+                    lambda: hamming_knn_batch_workspace_size(h, pairs.shape[0], out_rows))
     return idx, dist, accept
 
 
@@ -494,6 +543,18 @@ class Latch:
 
     def extract_batch(self, table, n_images, image_id, kps, desc=None, n_kps=None, stream=None):
         return latch_extract_batch(self.h, table, n_images, image_id, kps, desc, n_kps, stream)
+
+    def reserve(self, nbytes=0):
+        return latch_reserve(self.h, nbytes)
+
+    def knn_workspace_size(self, nq, nt, path="auto"):
+        return hamming_knn_workspace_size(self.h, nq, nt, path)
+
+    def knn_batch_workspace_size(self, n_pairs, out_rows):
+        return hamming_knn_batch_workspace_size(self.h, n_pairs, out_rows)
+
+    def detect_workspace_size(self, height, width):
+        return latch_detect_workspace_size(self.h, height, width)
 
     def knn(self, query, train, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn(self.h, query, train, k, ratio, path, **kw)

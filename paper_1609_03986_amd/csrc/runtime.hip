@@ -220,20 +220,37 @@ void assign_slots(const uint2 *toff, int waves, int per_wave, int group, int col
     cache.emplace(std::move(key), std::vector<uint8_t>(slot_of, slot_of + n));
 }
 
-int ensure_workspace(latch_handle h, size_t need)
+// Work calls never allocate or wait: a call whose need exceeds the handle's
+// workspace fails before it enqueues anything (latch_reserve sizes it).
+int check_workspace(latch_handle h, size_t need, const char *call)
 {
     if (need <= h->ws_bytes) return LATCH_OK;
-    size_t grow = need + need / 4;
-    // Work already enqueued may still use the old buffer.
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
-    if (h->ws) (void)hipFree(h->ws);
-    h->ws = nullptr;
-    h->ws_bytes = 0;
-    e = hipMalloc((void **)&h->ws, grow);
-    if (e != hipSuccess) return hip_fail(h, e, "hipMalloc(workspace)");
-    h->ws_bytes = grow;
-    return LATCH_OK;
+    return fail(h, LATCH_EWORKSPACE,
+                "%s needs %zu workspace bytes and the handle holds %zu: call latch_reserve first",
+                call, need, h->ws_bytes);
+}
+
+// Table uploads of handle creation: host arrays copied (or, with a null
+// source, zero-filled) on a private stream, waiting for that stream only.
+struct Upload {
+    void *dst;
+    const void *src;
+    size_t bytes;
+};
+
+hipError_t upload(const Upload *u, int n)
+{
+    hipStream_t s = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
+    for (int i = 0; i < n && e == hipSuccess; ++i)
+        e = u[i].src ? hipMemcpyAsync(u[i].dst, u[i].src, u[i].bytes, hipMemcpyHostToDevice, s)
+                     : hipMemsetAsync(u[i].dst, 0, u[i].bytes, s);
+    if (s) {
+        const hipError_t e2 = hipStreamSynchronize(s);
+        if (e == hipSuccess) e = e2;
+        (void)hipStreamDestroy(s);
+    }
+    return e;
 }
 
 hipEvent_t pool_event(latch_handle h)
@@ -324,6 +341,31 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
     return p;
 }
 
+// Partial top-2 keys of a split plan: 16 bytes per (split, query).
+size_t knn_workspace_bytes(const KnnPlan &p)
+{
+    return p.nsplit > 1 ? align_up((size_t)p.nsplit * p.nq * 2 * sizeof(uint64_t), 256) : 0;
+}
+
+// Detection: survivor masks (one u64 per row and 64-column tile), the first
+// output slot of every row, the per-(row, tile) survivor counts (rows padded
+// to 16 bytes) and the count on entry.
+struct DetectLayout {
+    size_t mask_bytes, first_bytes, count_bytes, total;
+    int count_stride;
+};
+
+DetectLayout detect_layout(int height, int width)
+{
+    DetectLayout l;
+    l.mask_bytes = align_up((size_t)height * ((width + 63) / 64) * sizeof(uint64_t), 256);
+    l.first_bytes = align_up((size_t)height * sizeof(int64_t), 256);
+    l.count_stride = (int)align_up((size_t)(width + 63) / 64, 16);
+    l.count_bytes = align_up((size_t)height * l.count_stride, 256);
+    l.total = l.mask_bytes + l.first_bytes + l.count_bytes + sizeof(int64_t);
+    return l;
+}
+
 size_t batch_workspace_bytes(int n_pairs, int64_t out_rows)
 {
     const int64_t item_capacity = out_rows / 256 + n_pairs + 1;
@@ -412,10 +454,12 @@ int create_base(latch_ctx **out)
     rotation_table(c, s);
     int2 rot[kBins];
     for (int a = 0; a < kBins; ++a) rot[a] = make_int2(c[a], s[a]);
-    if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) != hipSuccess ||
-        (e = hipMemcpy(h->rot_dev, rot, sizeof rot, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemset(h->flags_dev, 0, sizeof(uint32_t))) != hipSuccess) {
+    if ((e = hipMalloc((void **)&h->rot_dev, sizeof rot)) == hipSuccess &&
+        (e = hipMalloc((void **)&h->flags_dev, sizeof(uint32_t))) == hipSuccess) {
+        const Upload u[2] = {{h->rot_dev, rot, sizeof rot}, {h->flags_dev, nullptr, sizeof(uint32_t)}};
+        e = upload(u, 2);
+    }
+    if (e != hipSuccess) {
         const int rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
         latch_destroy(h);
         return rc;
@@ -479,13 +523,15 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
                              dense_patch_offset(tr[4], tr[5]));
     }
     hipError_t e;
-    if ((e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->dense_off_dev, sizeof doff)) != hipSuccess ||
-        (e = hipMemcpy(h->dense_off_dev, doff, sizeof doff, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(h->trip_off_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(h->unperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipDeviceSynchronize()) != hipSuccess) {
+    if ((e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) == hipSuccess &&
+        (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) == hipSuccess &&
+        (e = hipMalloc((void **)&h->dense_off_dev, sizeof doff)) == hipSuccess) {
+        const Upload u[3] = {{h->dense_off_dev, doff, sizeof doff},
+                             {h->trip_off_dev, toff_slot, sizeof toff_slot},
+                             {h->unperm_dev, unperm, sizeof unperm}};
+        e = upload(u, 3);
+    }
+    if (e != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
         latch_destroy(h);
         return rc;
@@ -551,11 +597,13 @@ int latch_create_geometry(latch_handle *out, const uint8_t *triplets_host, int w
             unperm[64 * w + (i & 63)] |= (uint32_t)slot_of[kWPerWave * w + i] << (8 * (i >> 6));
         }
     hipError_t e;
-    if ((e = hipMalloc((void **)&h->wtrip_dev, sizeof toff_slot)) != hipSuccess ||
-        (e = hipMalloc((void **)&h->wunperm_dev, sizeof unperm)) != hipSuccess ||
-        (e = hipMemcpy(h->wtrip_dev, toff_slot, sizeof toff_slot, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(h->wunperm_dev, unperm, sizeof unperm, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipDeviceSynchronize()) != hipSuccess) {
+    if ((e = hipMalloc((void **)&h->wtrip_dev, sizeof toff_slot)) == hipSuccess &&
+        (e = hipMalloc((void **)&h->wunperm_dev, sizeof unperm)) == hipSuccess) {
+        const Upload u[2] = {{h->wtrip_dev, toff_slot, sizeof toff_slot},
+                             {h->wunperm_dev, unperm, sizeof unperm}};
+        e = upload(u, 2);
+    }
+    if (e != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
         latch_destroy(h);
         return rc;
@@ -719,11 +767,8 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
         return fail(h, LATCH_ERANGE, "threshold %d (must be in [0, 255])", threshold);
     if (max_kps < 0 || max_kps > LATCH_MAX_ROWS)
         return fail(h, LATCH_EINVAL, "max_kps = %lld", (long long)max_kps);
-    const size_t mask_bytes = align_up((size_t)height * ((width + 63) / 64) * sizeof(uint64_t), 256);
-    const size_t first_bytes = align_up((size_t)height * sizeof(int64_t), 256);
-    const int count_stride = (int)align_up((size_t)(width + 63) / 64, 16);
-    const size_t count_bytes = align_up((size_t)height * count_stride, 256);
-    const int rc = ensure_workspace(h, mask_bytes + first_bytes + count_bytes + sizeof(int64_t));
+    const DetectLayout l = detect_layout(height, width);
+    const int rc = check_workspace(h, l.total, "latch_detect");
     if (rc != LATCH_OK) return rc;
     DetectArgs a;
     a.img = img_dev;
@@ -732,10 +777,10 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
     a.pitch = pitch;
     a.threshold = threshold;
     a.masks = reinterpret_cast<uint64_t *>(h->ws);
-    a.row_first = reinterpret_cast<int64_t *>(h->ws + mask_bytes);
-    a.counts = h->ws + mask_bytes + first_bytes;
-    a.count_stride = count_stride;
-    a.base = reinterpret_cast<int64_t *>(h->ws + mask_bytes + first_bytes + count_bytes);
+    a.row_first = reinterpret_cast<int64_t *>(h->ws + l.mask_bytes);
+    a.counts = h->ws + l.mask_bytes + l.first_bytes;
+    a.count_stride = l.count_stride;
+    a.base = reinterpret_cast<int64_t *>(h->ws + l.mask_bytes + l.first_bytes + l.count_bytes);
     a.kps = reinterpret_cast<float4 *>(kps_dev);
     a.max_kps = max_kps;
     a.n_kps = n_kps_dev;
@@ -775,8 +820,7 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
     a.dist = dist_dev;
     a.accept = accept_dev;
     if (a.plan.nsplit > 1) {
-        const size_t partial_bytes = align_up((size_t)a.plan.nsplit * nq * 2 * sizeof(uint64_t), 256);
-        const int rc = ensure_workspace(h, partial_bytes);
+        const int rc = check_workspace(h, knn_workspace_bytes(a.plan), "hamming_knn");
         if (rc != LATCH_OK) return rc;
         a.partial = reinterpret_cast<uint64_t *>(h->ws);
     }
@@ -792,6 +836,63 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
         e = timed_launch(h, "knn_merge", stream, [&] { return launch_knn_merge(a, stream); });
         if (e != hipSuccess) return hip_fail(h, e, "merge launch");
     }
+    return LATCH_OK;
+}
+
+int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path, size_t *bytes)
+{
+    if (!h || !bytes) return LATCH_EINVAL;
+    if (nq < 0 || nq > LATCH_MAX_ROWS || nt < 0 || nt > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "sizes nq = %lld, nt = %lld out of [0, 2^31)", (long long)nq,
+                    (long long)nt);
+    if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
+        return fail(h, LATCH_EINVAL, "unknown path %d", path);
+    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+    *bytes = nq == 0 ? 0 : knn_workspace_bytes(plan_knn(nq, nt, path, h->num_cus, h->tuning));
+    return LATCH_OK;
+}
+
+int hamming_knn_batch_workspace_size(latch_handle h, int n_pairs, int64_t out_rows, size_t *bytes)
+{
+    if (!h || !bytes) return LATCH_EINVAL;
+    if (n_pairs < 0 || out_rows < 0 || out_rows > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "negative or too large batch size");
+    *bytes = n_pairs == 0 ? 0 : batch_workspace_bytes(n_pairs, out_rows);
+    return LATCH_OK;
+}
+
+int latch_detect_workspace_size(latch_handle h, int height, int width, size_t *bytes)
+{
+    if (!h || !bytes) return LATCH_EINVAL;
+    if (height < 1 || width < 1 || height >= (1 << 23))
+        return fail(h, LATCH_EINVAL, "image %d x %d outside the limits", height, width);
+    *bytes = detect_layout(height, width).total;
+    return LATCH_OK;
+}
+
+int latch_reserve(latch_handle h, size_t bytes, size_t *held_out)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (bytes > h->ws_bytes) {
+        const size_t want = align_up(bytes, 256);
+        if (h->ws) {
+            // Work enqueued on any stream may still use the old buffer.
+            hipError_t e = hipDeviceSynchronize();
+            if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
+            (void)hipFree(h->ws);
+            h->ws = nullptr;
+            h->ws_bytes = 0;
+        }
+        const hipError_t e = hipMalloc((void **)&h->ws, want);
+        if (e != hipSuccess) {
+            h->ws = nullptr;
+            if (held_out) *held_out = 0;
+            return hip_fail(h, e, "hipMalloc(workspace)");
+        }
+        h->ws_bytes = want;
+    }
+    if (held_out) *held_out = h->ws_bytes;
     return LATCH_OK;
 }
 
@@ -870,7 +971,7 @@ int hamming_knn_batch(latch_handle h, const uint32_t *query_dev, int64_t query_r
         return fail(h, LATCH_EINVAL, "null buffer");
     if (path == LATCH_PATH_AUTO) path = h->tuning.batch_path;
 
-    int rc = ensure_workspace(h, batch_workspace_bytes(n_pairs, out_rows));
+    const int rc = check_workspace(h, batch_workspace_bytes(n_pairs, out_rows), "hamming_knn_batch");
     if (rc != LATCH_OK) return rc;
     const BatchArgs a = batch_args(h, h->ws, query_dev, query_rows, train_dev, train_rows,
                                    pairs_dev, n_pairs, k, ratio, idx_dev, dist_dev, accept_dev,

@@ -11,15 +11,20 @@ concurrently on self-contained streams (Sec. 4, "CUDA Integration").  Here
 that becomes a request loop.
 
   * Scheduler.  FIFO over arrived requests.  A request is admitted when a slot
-    is free and its HBM footprint fits the remaining budget.  A request larger
-    than the whole budget is rejected.
-  * Slots.  Each slot owns a HIP stream and a library handle, so admitted
-    requests run concurrently on the device.  A request that arrives while
-    others are in flight starts as soon as a slot and memory free up
-    (continuous batching).
+    is free and its HBM footprint fits what the budget leaves after the
+    memory the executor keeps (the slots' reserved workspaces).  A request
+    larger than that is rejected; one that waits longer than the timeout, or
+    that is cancelled, is dropped (a cancelled request already on the GPU
+    finishes there, and its result is discarded).
+  * Slots.  Each slot owns a HIP stream and a library handle whose workspace
+    is reserved once, at creation, for the largest request of the mix (the
+    library's own figure, hamming_knn_workspace_size), so admitted requests
+    run concurrently on the device and no request makes the library allocate
+    or wait.  A request that arrives while others are in flight starts as
+    soon as a slot and memory free up (continuous batching).
   * Executors.  GpuExecutor drives the C ABI through the binding.  The
-    scheduler only needs start / poll / finish, so tests can drive it with a
-    fake executor on the CPU.
+    scheduler only needs start / poll / finish and the memory figures, so
+    tests can drive it with a fake executor on the CPU.
 
 Latency is measured from a request's arrival to the completion of its results
 on the host.
@@ -60,38 +65,48 @@ class Result:
         return self.done - self.arrival
 
 
-def footprint_bytes(height, width, n_kps, db_rows, splits=32):
-    """Device bytes a request holds while in flight: image, keypoints,
-    descriptors, results and the matcher's split partials (16 B per query and
-    split; `splits` bounds the split count of one request's match)."""
+def footprint_bytes(height, width, n_kps, workspace_bytes=0):
+    """Device bytes a request holds while in flight: its image, keypoints,
+    descriptors and results, plus any matcher workspace it needs beyond what
+    its slot has reserved (`workspace_bytes`, from the executor, which asks
+    the library)."""
     return (height * width + n_kps * (KEYPOINT_BYTES + DESC_BYTES + RESULT_BYTES_PER_QUERY)
-            + n_kps * min(splits, max(1, db_rows // 256)) * 16)
+            + workspace_bytes)
 
 
 class Scheduler:
-    """FIFO admission by slot and HBM footprint; polls in-flight work."""
+    """FIFO admission by slot and HBM footprint, with a waiting timeout and
+    cancellation; polls in-flight work."""
 
     def __init__(self, executor, n_slots, hbm_budget, db_rows, clock=time.perf_counter,
-                 idle_sleep=50e-6):
+                 idle_sleep=50e-6, timeout_s=None):
         self.ex = executor
         self.n_slots = n_slots
         self.budget = hbm_budget
         self.db_rows = db_rows
         self.clock = clock
         self.idle_sleep = idle_sleep
+        self.timeout_s = timeout_s
+        self.cancelled = set()
 
     def footprint(self, req):
         h, w = req.image.shape
-        return footprint_bytes(h, w, len(req.kps), self.db_rows)
+        return footprint_bytes(h, w, len(req.kps), self.ex.workspace_bytes(len(req.kps)))
+
+    def cancel(self, rid):
+        """Drop request `rid`: before admission it never runs; in flight, its
+        result is discarded when it completes."""
+        self.cancelled.add(rid)
 
     def run(self, requests):
-        """Serve `requests` (sorted by arrival).  Returns (results, rejected ids, stats)."""
+        """Serve `requests` (sorted by arrival).  Returns (results, rejected ids,
+        stats); stats lists the ids that timed out or were cancelled."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         waiting = collections.deque()
         free = list(range(self.n_slots))
         inflight = {}                           # slot -> (request, footprint, admit time)
         used = 0
-        results, rejected = [], []
+        results, rejected, timed_out, dropped = [], [], [], []
         max_inflight = 0
         t0 = self.clock()
         while pending or waiting or inflight:
@@ -103,18 +118,34 @@ class Scheduler:
                 if self.ex.poll(slot):
                     req, fp, t_adm = inflight.pop(slot)
                     idx, dist, acc = self.ex.finish(slot)
-                    results.append(Result(req.rid, idx, dist, acc, req.arrival, t_adm,
-                                          self.clock() - t0))
+                    if req.rid in self.cancelled:
+                        dropped.append(req.rid)
+                    else:
+                        results.append(Result(req.rid, idx, dist, acc, req.arrival, t_adm,
+                                              self.clock() - t0))
                     used -= fp
                     free.append(slot)
+            # cancellations and time-outs of waiting requests
+            if waiting and (self.cancelled or self.timeout_s is not None):
+                now = self.clock() - t0
+                keep = collections.deque()
+                for r in waiting:
+                    if r.rid in self.cancelled:
+                        dropped.append(r.rid)
+                    elif self.timeout_s is not None and now - r.arrival > self.timeout_s:
+                        timed_out.append(r.rid)
+                    else:
+                        keep.append(r)
+                waiting = keep
             # admissions, in arrival order
             while waiting and free:
                 req = waiting[0]
                 fp = self.footprint(req)
-                if fp > self.budget:
+                room = self.budget - self.ex.retained_bytes()
+                if fp > room:
                     rejected.append(waiting.popleft().rid)
                     continue
-                if used + fp > self.budget:
+                if used + fp > room:
                     break
                 waiting.popleft()
                 slot = free.pop()
@@ -135,15 +166,17 @@ class Scheduler:
                  "throughput_rps": len(results) / wall if wall > 0 else 0.0,
                  "p50_ms": float(np.percentile(lat, 50) * 1e3),
                  "p99_ms": float(np.percentile(lat, 99) * 1e3),
-                 "max_inflight": max_inflight}
+                 "max_inflight": max_inflight, "timed_out": timed_out, "cancelled": dropped}
         return results, rejected, stats
 
 
 class GpuExecutor:
     """Runs requests on the GPU, one library handle and one HIP stream per slot,
-    matching against a device-resident database (torch int32 [N, 16])."""
+    matching against a device-resident database (torch int32 [N, 16]).  Each
+    slot's workspace is reserved at creation for every request of up to
+    `max_kps` keypoints."""
 
-    def __init__(self, db, triplets, n_slots, ratio=0.8, path="auto"):
+    def __init__(self, db, triplets, n_slots, ratio=0.8, path="auto", max_kps=50000):
         import torch
         from .binding import Latch
         self.torch = torch
@@ -152,8 +185,31 @@ class GpuExecutor:
         self.path = path
         self.slots = []
         for _ in range(n_slots):
-            self.slots.append({"stream": torch.cuda.Stream(), "lat": Latch(triplets),
-                               "event": None, "out": None})
+            lat = Latch(triplets)
+            self.slots.append({"stream": torch.cuda.Stream(), "lat": lat, "event": None,
+                               "out": None})
+        self.reserved = self.largest_workspace(max_kps)
+        for s in self.slots:
+            s["lat"].reserve(self.reserved)
+
+    def workspace_need(self, n_kps):
+        """The library's workspace figure for matching n_kps queries against the database."""
+        return self.slots[0]["lat"].knn_workspace_size(n_kps, self.db.shape[0], self.path)
+
+    def largest_workspace(self, max_kps):
+        """The largest need of any request of 1 .. max_kps keypoints.  The need
+        grows with the query count while the number of 256-query groups stays
+        fixed, so the largest of each group count is at its last count."""
+        counts = sorted({min(max_kps, 256 * g) for g in range(1, -(-max_kps // 256) + 1)})
+        return max(self.workspace_need(n) for n in counts)
+
+    def workspace_bytes(self, n_kps):
+        """Workspace a request needs beyond its slot's reservation."""
+        return max(0, self.workspace_need(n_kps) - self.reserved)
+
+    def retained_bytes(self):
+        """Device memory the slots keep across requests (their workspaces)."""
+        return sum(s["lat"].reserve(0) for s in self.slots)
 
     def start(self, slot, req):
         torch = self.torch
@@ -221,6 +277,15 @@ def make_requests(n, qps, pool, seed=11):
     return reqs
 
 
+def max_requests(n, pool, seed=98):
+    """n simultaneous requests of the mix's largest size (4000x3000, 50,000
+    keypoints): a warm-up that touches every slot at its largest footprint."""
+    from . import synth
+    g = np.random.default_rng(seed)
+    hw = SIZES[-1]
+    return [Request(i, pool[hw][0], synth.random_keypoints(g, 50000, *hw), 0.0) for i in range(n)]
+
+
 def build_database(lat, rows=1_000_000, images=50, seed=3):
     """`rows` descriptors extracted on the GPU from `images` seeded 1920x1080
     images (20,000 keypoints each for the default sizes)."""
@@ -249,22 +314,27 @@ def main(argv=None):
     ap.add_argument("--db-rows", type=int, default=1_000_000)
     ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--hbm-budget-gb", type=float, default=8.0)
-    ap.add_argument("--path", default="auto", choices=["auto", "mfma", "popcount"])
+    ap.add_argument("--path", default="auto", choices=["auto", "mfma", "fp4", "popcount"])
+    ap.add_argument("--timeout-s", type=float, default=None,
+                    help="drop requests that wait longer than this before admission")
     args = ap.parse_args(argv)
     trip = synth.triplet_table()
     builder = Latch(trip)
     db = build_database(builder, args.db_rows)
     pool = request_pool()
     ex = GpuExecutor(db, trip, args.slots, path=args.path)
-    sched = Scheduler(ex, args.slots, int(args.hbm_budget_gb * 2 ** 30), args.db_rows)
-    warm = make_requests(4, 1000.0, pool, seed=99)
+    sched = Scheduler(ex, args.slots, int(args.hbm_budget_gb * 2 ** 30), args.db_rows,
+                      timeout_s=args.timeout_s)
+    warm = max_requests(args.slots, pool)
     sched.run(warm)
     for qps in args.qps:
         reqs = make_requests(args.requests, qps, pool, seed=int(qps))
         results, rejected, stats = sched.run(reqs)
         pairs = sum(len(r.idx) for r in results) * args.db_rows
         stats.update({"offered_qps": qps, "db_rows": args.db_rows, "slots": args.slots,
-                      "pairs_per_s": pairs / stats["wall_s"], "path": args.path})
+                      "pairs_per_s": pairs / stats["wall_s"], "path": args.path,
+                      "slot_workspace_bytes": ex.reserved,
+                      "timed_out": len(stats["timed_out"]), "cancelled": len(stats["cancelled"])})
         print(json.dumps(stats), flush=True)
     ex.close()
     builder.close()

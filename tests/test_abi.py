@@ -98,3 +98,14 @@ def test_geometry_arguments_are_checked_before_touching_the_device(lib):
     assert create(bad.ctypes.data_as(P), 64, 8) == binding.LATCH_ERANGE
     h = ctypes.c_void_p()
     assert lib.latch_create_geometry(ctypes.byref(h), None, 64, 8, None) == binding.LATCH_EINVAL
+
+
+def test_workspace_calls_reject_null_arguments(lib):
+    from paper_1609_03986_amd import binding
+    n = ctypes.c_size_t(7)
+    assert lib.latch_reserve(None, 100, ctypes.byref(n)) == binding.LATCH_EINVAL
+    assert lib.hamming_knn_workspace_size(None, 10, 10, 0, ctypes.byref(n)) == binding.LATCH_EINVAL
+    assert lib.hamming_knn_batch_workspace_size(None, 1, 10, ctypes.byref(n)) == binding.LATCH_EINVAL
+    assert lib.latch_detect_workspace_size(None, 10, 10, ctypes.byref(n)) == binding.LATCH_EINVAL
+    assert n.value == 7
+    assert binding.STATUS_NAMES[binding.LATCH_EWORKSPACE] == "LATCH_EWORKSPACE"

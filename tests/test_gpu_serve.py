@@ -78,7 +78,19 @@ def test_full_size_database_sampled(torch_cuda, triplets):
         reqs = serve.make_requests(3, 100.0, pool)
         ex = serve.GpuExecutor(db, triplets, n_slots=2)
         try:
+            # Admission uses the library's own workspace figures: on the
+            # default MXFP4 path a 1M-row database needs at least 62 splits
+            # of 2^14 rows, 16 bytes per query and split, and every slot has
+            # reserved the largest need of the mix up front.
+            for n in (500, 5000, 25000, 50000):
+                need = ex.workspace_need(n)
+                assert need == lat.knn_workspace_size(n, 1_000_000, "auto")
+                assert need >= 62 * 16 * n
+                assert ex.workspace_bytes(n) == 0
+            assert ex.reserved >= ex.workspace_need(50000)
+            assert ex.retained_bytes() == 2 * ex.slots[0]["lat"].reserve(0) >= 2 * ex.reserved
             results, rej, stats = serve.Scheduler(ex, 2, 1 << 36, len(db_np)).run(reqs)
+            assert ex.retained_bytes() == 2 * ex.slots[0]["lat"].reserve(0)   # nothing grew
         finally:
             ex.close()
         assert not rej and stats["served"] == 3

@@ -11,10 +11,20 @@ from paper_1609_03986_amd import serve, synth
 
 
 class FakeExecutor:
-    def __init__(self, db, triplets, duration=0.01):
+    """Oracle results after a simulated duration.  Memory figures: `retained`
+    bytes kept across requests, and `extra(n_kps)` workspace beyond it."""
+
+    def __init__(self, db, triplets, duration=0.01, retained=0, extra=lambda n: 0):
         self.db, self.trip, self.duration = db, triplets, duration
+        self.retained, self.extra = retained, extra
         self.slots = {}
         self.started = []
+
+    def workspace_bytes(self, n_kps):
+        return self.extra(n_kps)
+
+    def retained_bytes(self):
+        return self.retained
 
     def start(self, slot, req):
         assert slot not in self.slots, "slot reused while busy"
@@ -64,7 +74,7 @@ def test_overlapping_arrivals_run_concurrently(db, triplets):
 
 def test_hbm_budget_limits_inflight_work(db, triplets):
     reqs = small_requests(5, 0.0)
-    fp = serve.footprint_bytes(60, 80, 20, len(db))
+    fp = serve.footprint_bytes(60, 80, 20)
     ex = FakeExecutor(db, triplets, 0.01)
     sched = serve.Scheduler(ex, n_slots=4, hbm_budget=2 * fp, db_rows=len(db))
     results, rejected, stats = sched.run(reqs)
@@ -81,7 +91,7 @@ def test_request_larger_than_budget_is_rejected(db, triplets):
     small = small_requests(2, 0.0, seed=3)
     for i, r in enumerate(small):
         r.rid = i + 1
-    budget = serve.footprint_bytes(60, 80, 20, len(db)) + 10
+    budget = serve.footprint_bytes(60, 80, 20) + 10
     sched = serve.Scheduler(FakeExecutor(db, triplets, 0.001), 2, budget, len(db))
     results, rejected, stats = sched.run([big] + small)
     assert rejected == [0]
@@ -97,3 +107,63 @@ def test_poisson_arrivals_and_request_mix_are_seeded():
     assert 0.3 / 100 < gaps.mean() < 3.0 / 100
     n = np.array([len(r.kps) for r in a])
     assert n.min() >= 500 and n.max() <= 50000
+
+
+def test_footprint_counts_image_keypoints_results_and_workspace():
+    assert serve.footprint_bytes(10, 20, 0) == 200
+    assert serve.footprint_bytes(10, 20, 3) == 200 + 3 * (16 + 64 + 17)
+    assert serve.footprint_bytes(10, 20, 3, workspace_bytes=1000) == 200 + 3 * 97 + 1000
+
+
+def test_retained_memory_and_extra_workspace_count_against_the_budget(db, triplets):
+    fp = serve.footprint_bytes(60, 80, 20)
+    # Retained memory leaves room for exactly one request at a time.
+    ex = FakeExecutor(db, triplets, 0.01, retained=10_000_000)
+    sched = serve.Scheduler(ex, n_slots=4, hbm_budget=10_000_000 + fp + fp // 2, db_rows=len(db))
+    results, rejected, stats = sched.run(small_requests(3, 0.0))
+    assert stats["served"] == 3 and not rejected and stats["max_inflight"] == 1
+    # Retained memory above the budget: every request is rejected.
+    ex = FakeExecutor(db, triplets, 0.001, retained=1 << 40)
+    results, rejected, stats = serve.Scheduler(ex, 2, 1 << 30, len(db)).run(small_requests(2, 0.0))
+    assert rejected == [0, 1] and not results
+    # A request whose extra workspace does not fit is rejected; the others run.
+    ex = FakeExecutor(db, triplets, 0.001, extra=lambda n: 1 << 40 if n == 21 else 0)
+    reqs = small_requests(3, 0.0)
+    g = np.random.default_rng(9)
+    reqs[1].kps = synth.random_keypoints(g, 21, 60, 80)
+    results, rejected, stats = serve.Scheduler(ex, 2, 1 << 30, len(db)).run(reqs)
+    assert rejected == [1] and sorted(r.rid for r in results) == [0, 2]
+    assert serve.Scheduler(ex, 2, 1 << 30, len(db)).footprint(reqs[1]) == \
+        serve.footprint_bytes(60, 80, 21, 1 << 40)
+
+
+def test_waiting_requests_time_out(db, triplets):
+    # One slot, each request takes 30 ms: with a 10 ms timeout the requests
+    # queued behind the first are dropped before admission.
+    ex = FakeExecutor(db, triplets, 0.03)
+    sched = serve.Scheduler(ex, n_slots=1, hbm_budget=1 << 30, db_rows=len(db), timeout_s=0.01)
+    results, rejected, stats = sched.run(small_requests(4, 0.0))
+    assert [r.rid for r in results] == [0]
+    assert sorted(stats["timed_out"]) == [1, 2, 3] and ex.started == [0]
+
+
+def test_cancelled_requests_are_dropped(db, triplets):
+    ex = FakeExecutor(db, triplets, 0.02)
+    sched = serve.Scheduler(ex, n_slots=1, hbm_budget=1 << 30, db_rows=len(db))
+    sched.cancel(2)
+    results, rejected, stats = sched.run(small_requests(4, 0.001))
+    assert sorted(r.rid for r in results) == [0, 1, 3]
+    assert stats["cancelled"] == [2] and 2 not in ex.started
+
+
+def test_cancelled_in_flight_result_is_discarded(db, triplets):
+    class CancelOnStart(FakeExecutor):
+        def start(self, slot, req):
+            super().start(slot, req)
+            if req.rid == 1:
+                sched.cancel(1)
+    ex = CancelOnStart(db, triplets, 0.005)
+    sched = serve.Scheduler(ex, n_slots=2, hbm_budget=1 << 30, db_rows=len(db))
+    results, rejected, stats = sched.run(small_requests(3, 0.0))
+    assert sorted(r.rid for r in results) == [0, 2] and stats["cancelled"] == [1]
+    assert 1 in ex.started
