@@ -308,6 +308,27 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
                 int32_t *idx_dev, int32_t *dist_dev, uint8_t *accept_dev, int path,
                 hipStream_t stream);
 
+/*
+ * Allocation-free hamming_knn, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, checks and results as hamming_knn, but the
+ * split partials live in a static device array of LATCH_NOALLOC_SCRATCH_BYTES
+ * that the library holds on every GPU it runs on until the process ends, not
+ * in the handle's workspace: the call never allocates, frees or reserves, and
+ * records no timing events.  The split plan is the one hamming_knn_workspace_size
+ * prices; a call whose partials would exceed the scratch (16 bytes per
+ * (query, train split) when the train rows are split) returns LATCH_ERANGE
+ * and enqueues nothing.  Every call on one GPU shares that GPU's scratch:
+ * calls that overlap in time on one GPU (any handle, any stream) race, so
+ * order them on one stream.  The scratch keeps the last call's contents;
+ * nothing in it needs to start at zero.
+ */
+#define LATCH_NOALLOC_SCRATCH_BYTES (16u << 20)
+int hamming_knn_noalloc(latch_handle h, const uint32_t *query_dev, int64_t nq,
+                        const uint32_t *train_dev, int64_t nt, int k, float ratio,
+                        int32_t *idx_dev, int32_t *dist_dev, uint8_t *accept_dev, int path,
+                        hipStream_t stream);
+
 /* One pair of a batched matching (device memory), 40 bytes. */
 typedef struct {
     int64_t query_first;  /* first row of this pair's queries in query_dev */

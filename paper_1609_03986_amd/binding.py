@@ -36,7 +36,7 @@ EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "hamming_kn
            "hamming_knn_batch_workspace_size", "latch_detect_workspace_size", "latch_reserve",
            "latch_extract", "latch_extract_batch",
            "latch_extract_dense", "hamming_knn_window", "latch_detect",
-           "hamming_knn",
+           "hamming_knn", "hamming_knn_noalloc",
            "hamming_knn_batch", "latch_plan_create", "latch_plan_run", "latch_plan_destroy",
            "latch_get_tuning", "latch_set_tuning",
            "latch_check_errors",
@@ -95,6 +95,8 @@ def load_library():
     lib.latch_detect.argtypes = [P, P, I, I, I, I, P, I64, P, P, I, P]
     lib.latch_detect.restype = I
     lib.hamming_knn.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
+    lib.hamming_knn_noalloc.argtypes = [P, P, I64, P, I64, I, F, P, P, P, I, P]
+    lib.hamming_knn_noalloc.restype = I
     lib.hamming_knn_batch.argtypes = [P, P, I64, P, I64, P, I, I, F, P, P, P, I64, I, P]
     lib.hamming_knn_batch.restype = I
     lib.latch_plan_create.argtypes = [P, P, ctypes.POINTER(P)]
@@ -370,6 +372,25 @@ def hamming_knn(h, query, train, k=2, ratio=0.8, path="auto", idx=None, dist=Non
     _with_workspace(h, lambda: load_library().hamming_knn(*args),
                     lambda: hamming_knn_workspace_size(h, nq, nt, path))
     return idx, dist, accept
+
+
+def hamming_knn_noalloc(h, query, train, idx, dist, accept=None, k=2, ratio=0.8, path="auto",
+                        stream=None):
+    """hamming_knn with its split partials in the library's static device
+    scratch: the caller passes every output (idx, dist int32 [nq, k], accept
+    uint8 [nq] or None) and nothing is allocated."""
+    import torch
+    nq, nt = query.shape[0], train.shape[0]
+    acc_ptr = _dev(accept, torch.uint8, "accept") if accept is not None else None
+    tptr = _dev(train, torch.int32, "train") if nt > 0 else None
+    _check(h, load_library().hamming_knn_noalloc(
+        h, _dev(query, torch.int32, "query"), nq, tptr, nt, int(k), float(ratio),
+        _dev(idx, torch.int32, "idx"), _dev(dist, torch.int32, "dist"), acc_ptr, PATHS[path],
+        _stream_ptr(stream)))
+    return idx, dist, accept
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20     # LATCH_NOALLOC_SCRATCH_BYTES
 
 
 def pair_table(pairs, device="cuda"):

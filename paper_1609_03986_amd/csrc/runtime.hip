@@ -30,6 +30,7 @@ struct latch_ctx {
     WeightRows weights = {};
     uint8_t *ws = nullptr;             // grow-only workspace
     size_t ws_bytes = 0;
+    uint8_t *scratch = nullptr;        // this device's copy of the static scratch array
     latch_tuning tuning;               // LATCH_PATH_AUTO table and split targets
     std::string last_error;
     // Event timing (latch_timing_enable).
@@ -438,6 +439,31 @@ hipError_t run_extract(const ExtractArgs &a, hipStream_t stream)
     return a.window ? launch_extract_weighted(a, stream) : launch_extract(a, stream);
 }
 
+// Scratch of hamming_knn_noalloc: a static device array, one copy per GPU
+// the library runs on, held until the process ends.  Host code never names
+// it directly (on the host `scratch` is only a stand-in symbol): it uses the
+// device address hipGetSymbolAddress gives, looked up once per device.
+static __device__ __align__(256) uint8_t scratch[LATCH_NOALLOC_SCRATCH_BYTES];
+
+std::mutex scratch_mutex;
+std::map<int, uint8_t *> scratch_by_device;
+
+// Address of `device`'s copy of the scratch array; `device` must be current.
+hipError_t scratch_address(int device, uint8_t **out)
+{
+    std::lock_guard<std::mutex> lock(scratch_mutex);
+    auto it = scratch_by_device.find(device);
+    if (it == scratch_by_device.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!ptr) return hipErrorInvalidSymbol;
+        it = scratch_by_device.emplace(device, static_cast<uint8_t *>(ptr)).first;
+    }
+    *out = it->second;
+    return hipSuccess;
+}
+
 // A handle with the rotation table and the error word (no triplet data).
 int create_base(latch_ctx **out)
 {
@@ -446,6 +472,7 @@ int create_base(latch_ctx **out)
     hipError_t e = hipGetDevice(&h->device);
     if (e == hipSuccess)
         e = hipDeviceGetAttribute(&h->num_cus, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (e == hipSuccess && h->num_cus >= 1) e = scratch_address(h->device, &h->scratch);
     if (e != hipSuccess || h->num_cus < 1) {
         delete h;
         return LATCH_EDEVICE;
@@ -465,6 +492,73 @@ int create_base(latch_ctx **out)
         return rc;
     }
     *out = h;
+    return LATCH_OK;
+}
+
+// hamming_knn and hamming_knn_noalloc: the same checks and launches; the
+// split partials go to the handle's workspace or to the static scratch.
+int knn_call(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32_t *train_dev,
+             int64_t nt, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
+             uint8_t *accept_dev, int path, hipStream_t stream, bool noalloc)
+{
+    if (!h) return LATCH_EINVAL;
+    h->last_error.clear();
+    if (nq < 0 || nq > LATCH_MAX_ROWS || nt < 0 || nt > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "sizes nq = %lld, nt = %lld out of [0, 2^31)", (long long)nq,
+                    (long long)nt);
+    if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
+    if (!(ratio > 0.0f && ratio <= 1.0f))
+        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
+    if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
+        return fail(h, LATCH_EINVAL, "unknown path %d", path);
+    if (nq == 0) return LATCH_OK;
+    if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
+        return fail(h, LATCH_EINVAL, "null buffer");
+    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+
+    KnnSplitArgs a;
+    a.query = query_dev;
+    a.train = train_dev;
+    a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
+    a.partial = nullptr;
+    a.k = k;
+    a.ratio = ratio;
+    a.idx = idx_dev;
+    a.dist = dist_dev;
+    a.accept = accept_dev;
+    if (a.plan.nsplit > 1) {
+        const size_t need = knn_workspace_bytes(a.plan);
+        if (noalloc) {
+            // Every (split, query) partial is written by the split kernel
+            // before the merge reads it, so nothing needs clearing.
+            if (need > LATCH_NOALLOC_SCRATCH_BYTES)
+                return fail(h, LATCH_ERANGE,
+                            "hamming_knn_noalloc needs %zu scratch bytes (%d train splits x %lld "
+                            "queries) and its static scratch holds %zu",
+                            need, a.plan.nsplit, (long long)nq, (size_t)LATCH_NOALLOC_SCRATCH_BYTES);
+            a.partial = reinterpret_cast<uint64_t *>(h->scratch);
+        } else {
+            const int rc = check_workspace(h, need, "hamming_knn");
+            if (rc != LATCH_OK) return rc;
+            a.partial = reinterpret_cast<uint64_t *>(h->ws);
+        }
+    }
+    const SplitKernel which = path == LATCH_PATH_MFMA       ? SplitKernel::kMfmaI8
+                              : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
+                                                            : SplitKernel::kPopcount;
+    const char *name = which == SplitKernel::kMfmaI8    ? "knn_mfma"
+                       : which == SplitKernel::kMfmaFp4 ? "knn_fp4"
+                                                        : "knn_popcount";
+    // The allocation-free call records no timing events (creating one may allocate).
+    auto launch = [&](const char *what, auto &&f) {
+        return noalloc ? f() : timed_launch(h, what, stream, f);
+    };
+    hipError_t e = launch(name, [&] { return launch_knn_split(a, which, stream); });
+    if (e != hipSuccess) return hip_fail(h, e, name);
+    if (a.plan.nsplit > 1) {
+        e = launch("knn_merge", [&] { return launch_knn_merge(a, stream); });
+        if (e != hipSuccess) return hip_fail(h, e, "merge launch");
+    }
     return LATCH_OK;
 }
 
@@ -794,49 +888,17 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq, const uin
                 int64_t nt, int k, float ratio, int32_t *idx_dev, int32_t *dist_dev,
                 uint8_t *accept_dev, int path, hipStream_t stream)
 {
-    if (!h) return LATCH_EINVAL;
-    h->last_error.clear();
-    if (nq < 0 || nq > LATCH_MAX_ROWS || nt < 0 || nt > LATCH_MAX_ROWS)
-        return fail(h, LATCH_EINVAL, "sizes nq = %lld, nt = %lld out of [0, 2^31)", (long long)nq,
-                    (long long)nt);
-    if (k != 1 && k != 2) return fail(h, LATCH_ERANGE, "k = %d (must be 1 or 2)", k);
-    if (!(ratio > 0.0f && ratio <= 1.0f))
-        return fail(h, LATCH_ERANGE, "ratio = %g (must be in (0, 1])", (double)ratio);
-    if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
-        return fail(h, LATCH_EINVAL, "unknown path %d", path);
-    if (nq == 0) return LATCH_OK;
-    if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
-        return fail(h, LATCH_EINVAL, "null buffer");
-    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+    return knn_call(h, query_dev, nq, train_dev, nt, k, ratio, idx_dev, dist_dev, accept_dev, path,
+                    stream, false);
+}
 
-    KnnSplitArgs a;
-    a.query = query_dev;
-    a.train = train_dev;
-    a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
-    a.partial = nullptr;
-    a.k = k;
-    a.ratio = ratio;
-    a.idx = idx_dev;
-    a.dist = dist_dev;
-    a.accept = accept_dev;
-    if (a.plan.nsplit > 1) {
-        const int rc = check_workspace(h, knn_workspace_bytes(a.plan), "hamming_knn");
-        if (rc != LATCH_OK) return rc;
-        a.partial = reinterpret_cast<uint64_t *>(h->ws);
-    }
-    const SplitKernel which = path == LATCH_PATH_MFMA       ? SplitKernel::kMfmaI8
-                              : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
-                                                            : SplitKernel::kPopcount;
-    const char *name = which == SplitKernel::kMfmaI8    ? "knn_mfma"
-                       : which == SplitKernel::kMfmaFp4 ? "knn_fp4"
-                                                        : "knn_popcount";
-    hipError_t e = timed_launch(h, name, stream, [&] { return launch_knn_split(a, which, stream); });
-    if (e != hipSuccess) return hip_fail(h, e, name);
-    if (a.plan.nsplit > 1) {
-        e = timed_launch(h, "knn_merge", stream, [&] { return launch_knn_merge(a, stream); });
-        if (e != hipSuccess) return hip_fail(h, e, "merge launch");
-    }
-    return LATCH_OK;
+int hamming_knn_noalloc(latch_handle h, const uint32_t *query_dev, int64_t nq,
+                        const uint32_t *train_dev, int64_t nt, int k, float ratio,
+                        int32_t *idx_dev, int32_t *dist_dev, uint8_t *accept_dev, int path,
+                        hipStream_t stream)
+{
+    return knn_call(h, query_dev, nq, train_dev, nt, k, ratio, idx_dev, dist_dev, accept_dev, path,
+                    stream, true);
 }
 
 int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path, size_t *bytes)
