@@ -1,22 +1,27 @@
 """Benchmark: LATCH extraction + 2-NN Hamming matching on one MI355X.
 
-One step is one pass of the whole path over one synthetic image pair:
-  extract 10,000 descriptors from each of two 1920x1080 u8 images (angle
-  U[0, 360), scale 1.2^U{0..7}) in one batched launch, then match the 10,000
-  query descriptors 2-NN against the 10,000 train descriptors with ratio 0.8
-  (matcher path from the handle's tuning table unless --path is given).
-Inputs are resident in HBM before the timed region starts.
+One step is one replay of the SfM batch plan (a HIP graph captured once by
+latch_plan_create): extraction of 20,000 oriented, scaled keypoints in each of
+64 images of 3000x2000 u8 (1.28 M descriptors, one batched launch), then 2-NN
+matching with ratio 0.8 over the 63 consecutive image pairs, 20,000 x 20,000
+each (2.52e10 pairs, one persistent batched launch).  The images are crops of
+one textured mosaic (a synthetic stand-in for a photogrammetry scene, the
+setting of the paper's Sec. 5).  Inputs are resident in HBM before the timed
+region starts.
 
 Prints one JSON line.  `value` is descriptors extracted and matched per
-second for the whole step (20,000 descriptors per step).  Extra fields give
-the component rates (extraction desc/s, matching pairs/s per path,
-FAST detection of both images, the weighted 64 x 64 / 8 x 8 geometry, dense
-per-pixel descriptors and windowed matching), step
-latency percentiles, per-kernel durations from HIP events recorded by the
-library on its launch stream, the roofline of the dominant kernel and the
-CPU oracle baseline.
+second for the whole step; `pairs_per_s` the matched pairs per second.  The
+roofline object covers the step's dominant kernel: its average duration
+comes from HIP events the library records on its launch stream around each
+kernel, in a run of the same launches (the graph holds the same two kernels
+with the same arguments).  Components: the same batch as one call per image
+and per pair (the plain form), the PCIe-inclusive step, a 1920x1080 image
+pair (extraction, and matching on every matcher path), the uneven 256-image
+batch as a plan, a short serving run against a 1,000,000-row resident
+database, FAST detection, the weighted 64 x 64 / 8 x 8 geometry and dense
+per-pixel descriptors with windowed matching.
 
-    python bench.py [--gpus 1] [--steps 500] [--warmup 300] [--path mfma|fp4|popcount]
+    python bench.py [--gpus 1] [--steps 20] [--warmup 5]
 """
 import argparse
 import json
@@ -30,47 +35,60 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "LATCH desc/s + Hamming pairs/s (MFMA vs popcount) at 1 GPU; p50/p99 ms"
-WORKLOAD = ("1920x1080 u8 image pair, 10,000 keypoints each (angle U[0,360), scale 1.2^U{0..7}), "
-            "512-bit LATCH over 48x48 windows with 7x7 patches, then 10,000 x 10,000 "
-            "brute-force 2-NN Hamming matching with ratio 0.8")
+WORKLOAD = ("SfM batch: 64 images of 3000x2000 u8 (crops of one textured mosaic), 20,000 "
+            "keypoints each (angle U[0,360), scale 1.2^U{0..7}), 512-bit LATCH over 48x48 "
+            "windows with 7x7 patches (1.28 M descriptors), then brute-force 2-NN Hamming "
+            "matching with ratio 0.8 over the 63 consecutive image pairs (20,000 x 20,000 each), "
+            "replayed as one captured plan")
 
 # MI355X published peaks and chip constants.
 PEAK_HBM_GBS = 8000.0
 PEAK_INT8_MFMA_TOPS = 5000.0           # dense int8 MFMA, 10^12 ops/s
 PEAK_FP4_MFMA_TOPS = 10100.0           # dense FP4 MFMA, 10^12 ops/s
+PEAK_VECTOR_TOPS = 157.3               # published vector peak (fp32), 10^12 ops/s
 CUS, CLOCK_GHZ, LANES = 256, 2.4, 64
+# One 32-bit integer VALU operation per lane per cycle.
+PEAK_INT_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0         # 39.3
 # Integer VALU with v_dot4_u32_u8: 4 byte MACs = 8 ops per lane per cycle.
-PEAK_DOT4_TOPS = CUS * LANES * CLOCK_GHZ * 8 / 1000.0   # 314.6
-# Algorithmic work per unit: per descriptor, 512 triplets x 2 distances x 49 squared
-# differences x 3 integer ops; per matched pair, the 512 MACs of a.b.
-EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 3                  # sub, mul, add per squared difference
-MATCH_OPS_PER_PAIR = 512 * 2                             # 512 MACs of a.b
+PEAK_DOT4_TOPS = PEAK_INT_TOPS * 8                       # 314.6
+# v_dot2_i32_i16: 2 MACs = 4 ops per lane per cycle.
+PEAK_DOT2_TOPS = PEAK_INT_TOPS * 4                       # 157.3
+# Algorithmic work per unit.  Extraction: per descriptor 512 triplets x 2
+# patch distances x 49 squared differences, 2 operations each (subtract,
+# multiply-accumulate).  Matching: per pair the 512 multiply-accumulates of
+# a.b (1,024 operations).
+EXTRACT_OPS_PER_DESC = 512 * 2 * 49 * 2                  # 100,352
+MATCH_OPS_PER_PAIR = 512 * 2
+POPCOUNT_OPS_PER_PAIR = 32                               # 16 XOR + 16 popcount-accumulate
 DETECT_THRESHOLD = 20                                    # FAST threshold of the detection component
 # Weighted CLATCH geometry: per descriptor 512 x 2 x 64 weighted squared
-# differences x 4 ops (sub, square, weight, add), against the chip's
-# v_dot2_i32_i16 rate (2 MACs = 4 ops per lane per cycle).
+# differences x 4 ops (sub, square, weight, add), against the v_dot2_i32_i16 rate.
 WEIGHTED_OPS_PER_DESC = 512 * 2 * 64 * 4
-PEAK_DOT2_TOPS = CUS * LANES * CLOCK_GHZ * 4 / 1000.0   # 157.3
 # Dense CLATCH: per pixel and triplet, G = (C1 - C2)(C1 + C2 - 2A) (4 ops), a
 # running sum down the rows (2), one across the columns (2) and the compare
-# (1); dense matching: 32 ops per candidate (16 XOR + 16 popcount-add).  Both
-# against the 32-bit integer VALU rate (one op per lane per cycle).
+# (1); dense matching: 32 ops per candidate.  Both against the 32-bit integer
+# VALU rate.
 DENSE_OPS_PER_PIXEL = 512 * 9
 DENSE_RADIUS = 4
-PEAK_INT_TOPS = CUS * LANES * CLOCK_GHZ / 1000.0         # 39.3
+TUNING_TABLE = os.path.join(ROOT, "paper_1609_03986_amd", "tuning.json")
+PAPER = {"clatch_extraction_us_per_desc": 0.5, "desc_per_s": 2.0e6,
+         "hardware": "NVIDIA GTX 970M", "source": "Table 1",
+         "matching": "no standalone matching rate reported (Sec. 4 describes the kernel only)"}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    # Defaults: 300 untimed steps (about 40 ms) bring the GPU to its steady
-    # clocks before the 500 timed ones (about 60 ms).
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=300)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--path", default="auto", choices=["auto", "mfma", "fp4", "popcount"],
-                    help="matcher path of the step (auto: the handle's tuning table)")
-    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="matcher path of the plan (auto: the handle's tuning table)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="approximate CPU time budget of the oracle baseline (0 = skip)")
+    ap.add_argument("--components", default="all",
+                    help="comma-separated components to run besides the headline step "
+                         "(all, none, or any of: plain, pcie, hd, uneven, serve, match_1m, "
+                         "detect, weighted, dense)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (3 times) and exit; "
                          "its FETCH_SIZE / WRITE_SIZE readings calibrate the HBM traffic counters")
@@ -88,13 +106,15 @@ def copy_calibration(mib):
     print(json.dumps({"copy_calibration_mib": mib, "bytes": mib << 20}), flush=True)
 
 
-def recorded_traffic(kernel):
+def recorded_traffic(kernel, workload):
     """HBM bytes per launch (calibrated FETCH_SIZE + WRITE_SIZE) recorded in
-    profiles/traffic.json for this kernel, or None when missing or when the
-    kernel's source has changed since the counters were taken."""
+    profiles/traffic.json for this kernel on this workload, or None when
+    missing or when the kernel's source has changed since the counters were
+    taken."""
     import hashlib
     try:
-        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"][kernel]
+        rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"]
+        rec = rec["%s@%s" % (kernel, workload)]
         src = open(os.path.join(ROOT, rec["source"]), "rb").read()
     except (OSError, KeyError, ValueError):
         return None
@@ -103,64 +123,40 @@ def recorded_traffic(kernel):
     return rec["read_bytes_per_launch"] + rec["write_bytes_per_launch"]
 
 
+def log(msg):
+    """Progress of the run, on stderr (the JSON line alone goes to stdout)."""
+    print("[bench %.1fs] %s" % (time.perf_counter() - T_START, msg), file=sys.stderr, flush=True)
+
+
+T_START = time.perf_counter()
+
+
 def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p))
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(requested --gpus %d)." % args.gpus, file=sys.stderr)
-        sys.exit(2)
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
+def load_tuning(lat):
+    """Install the in-tree autotuned table when it was measured on this
+    device and library version; returns a description of the table in use."""
+    from paper_1609_03986_amd import autotune
+    t = autotune.load(lat, TUNING_TABLE)
+    if t is None:
+        return {"source": "library default", "table": lat.get_tuning().to_dict()}
+    return {"source": os.path.relpath(TUNING_TABLE, ROOT), "key": autotune.cache_key(), "table": t}
 
-    import torch
-    from paper_1609_03986_amd import synth
-    from paper_1609_03986_amd.binding import Latch, image_table
 
-    torch.cuda.set_device(0)
-    dev = torch.device("cuda", 0)
-    w = synth.workload_hd()
-    trip = synth.triplet_table()
-    nq, nt = len(w["query_kps"]), len(w["train_kps"])
+class Timer:
+    """Wall time of repeated calls, bracketed by device synchronisation."""
 
-    img_q = torch.from_numpy(w["query_image"]).to(dev)
-    img_t = torch.from_numpy(w["train_image"]).to(dev)
-    # Both images' keypoints in one array, extracted by one batched launch
-    # (latch_extract_batch with a two-image table and per-keypoint image ids).
-    kps = torch.from_numpy(np.concatenate([w["query_kps"], w["train_kps"]])).to(dev)
-    kps_q, kps_t = kps[:nq], kps[nq:]
-    image_id = torch.from_numpy(np.repeat(np.arange(2, dtype=np.int32), [nq, nt])).to(dev)
-    table = image_table([img_q, img_t])
-    desc = torch.empty((nq + nt, 16), dtype=torch.int32, device=dev)
-    desc_q, desc_t = desc[:nq], desc[nq:]
-    idx = torch.empty((nq, 2), dtype=torch.int32, device=dev)
-    dist = torch.empty((nq, 2), dtype=torch.int32, device=dev)
-    acc = torch.empty((nq,), dtype=torch.uint8, device=dev)
-    lat = Latch(trip)
-    stream = torch.cuda.current_stream()
+    def __init__(self, torch):
+        self.torch = torch
 
-    def extract_both():
-        lat.extract_batch(table, 2, image_id, kps, desc)
-
-    def match(path):
-        lat.knn(desc_q, desc_t, k=2, ratio=0.8, path=path, idx=idx, dist=dist, accept=acc)
-
-    def step():
-        extract_both()
-        match(args.path)
-
-    def timed_loop(fn, steps, warmup, per_step=False):
-        """Wall time of `steps` calls, bracketed by device synchronisation.
-        With per_step, also each call's GPU time from an event pair around it
-        (the event packets themselves cost several microseconds per step, so
-        throughput is measured without them)."""
+    def loop(self, fn, steps, warmup=0, per_step=False):
+        torch = self.torch
         for _ in range(warmup):
             fn()
         torch.cuda.synchronize()
+        stream = torch.cuda.current_stream()
         if per_step:
             starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
             stops = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
@@ -176,49 +172,459 @@ def main():
         lat_ms = [s.elapsed_time(e) for s, e in zip(starts, stops)] if per_step else None
         return wall, lat_ms
 
-    # --- The timed region: exactly K whole steps. ---
-    wall, _ = timed_loop(step, args.steps, args.warmup)
-    # Step latency (p50 / p99) from a second, event-instrumented run of K steps.
-    _, step_ms = timed_loop(step, args.steps, 0, per_step=True)
-    ms_per_step = wall / args.steps * 1e3
-    value = (nq + nt) / (wall / args.steps)
 
-    # --- Per-kernel durations from the library's HIP events (same workload). ---
+def kernel_times(lat, torch, fn, reps, names):
+    """Average durations of the library's kernels over `reps` calls of fn,
+    from the HIP events the library records on its launch stream."""
     lat.timing(True)
-    for _ in range(args.steps):
-        step()
+    for _ in range(reps):
+        fn()
     torch.cuda.synchronize()
-    kernels = {}
-    for name in ("extract", "knn_mfma", "knn_fp4", "knn_popcount", "knn_merge"):
+    out = {}
+    for name in names:
         n, total = lat.timing_read(name)
         if n:
-            kernels[name] = {"launches_per_step": n / args.steps, "avg_ms": total / n,
-                             "ms_per_step": total / args.steps}
+            out[name] = {"launches_per_step": n / reps, "avg_ms": total / n,
+                         "ms_per_step": total / reps}
     lat.timing(False)
+    return out
 
-    # --- Component rates. ---
-    ex_wall, _ = timed_loop(extract_both, args.steps, 2)
-    extract_desc_s = (nq + nt) / (ex_wall / args.steps)
+
+class Batch:
+    """A batch of images on the device: image table, keypoints, image ids,
+    consecutive-pair table and output buffers, with its captured plan and the
+    same work as eager batched calls and as one call per image and pair."""
+
+    def __init__(self, torch, lat, imgs, kps, path):
+        from paper_1609_03986_amd.binding import image_table, pair_table
+        self.torch, self.lat, self.path = torch, lat, path
+        self.counts = [len(k) for k in kps]
+        self.first = np.concatenate([[0], np.cumsum(self.counts)[:-1]]).astype(np.int64)
+        self.total = int(sum(self.counts))
+        self.n_img = len(imgs)
+        self.dimgs = [torch.from_numpy(im).cuda() for im in imgs]
+        self.kp_all = torch.from_numpy(np.concatenate(kps).astype(np.float32)).cuda()
+        self.ids = torch.from_numpy(np.repeat(np.arange(self.n_img, dtype=np.int32),
+                                              self.counts)).cuda()
+        self.table = image_table(self.dimgs)
+        self.pairs_np = np.array([(self.first[i], self.counts[i], self.first[i + 1],
+                                   self.counts[i + 1], self.first[i])
+                                  for i in range(self.n_img - 1)], np.int64)
+        self.pairs = pair_table(self.pairs_np)
+        self.n_pairs = int(sum(self.counts[i] * self.counts[i + 1] for i in range(self.n_img - 1)))
+        self.desc = torch.empty((self.total, 16), dtype=torch.int32, device="cuda")
+        self.idx = torch.full((self.total, 2), -2, dtype=torch.int32, device="cuda")
+        self.dist = torch.full((self.total, 2), -2, dtype=torch.int32, device="cuda")
+        self.acc = torch.zeros(self.total, dtype=torch.uint8, device="cuda")
+        self.plan = lat.plan(self.table, self.n_img, self.ids, self.kp_all, self.desc, self.pairs,
+                             self.idx, self.dist, self.acc, path=path)
+        lat.reserve(lat.knn_batch_workspace_size(self.n_img - 1, self.total))
+
+    def run_plan(self):
+        self.plan.run()
+
+    def run_eager(self):
+        """The plan's two launches as eager calls (same kernels and arguments)."""
+        self.lat.extract_batch(self.table, self.n_img, self.ids, self.kp_all, self.desc)
+        self.lat.knn_batch(self.desc, self.desc, self.pairs, self.total, path=self.path,
+                           idx=self.idx, dist=self.dist, accept=self.acc)
+
+    def per_image_form(self):
+        """One latch_extract per image and one hamming_knn per pair, into
+        separate outputs; returns (run, outputs)."""
+        torch, lat = self.torch, self.lat
+        desc = torch.empty_like(self.desc)
+        idx = torch.full_like(self.idx, -2)
+        dist = torch.full_like(self.dist, -2)
+        acc = torch.zeros_like(self.acc)
+        ks = [self.kp_all[self.first[i]:self.first[i] + self.counts[i]] for i in range(self.n_img)]
+        ds = [desc[self.first[i]:self.first[i] + self.counts[i]] for i in range(self.n_img)]
+        need = max(lat.knn_workspace_size(self.counts[i], self.counts[i + 1], self.path)
+                   for i in range(self.n_img - 1))
+        lat.reserve(need)
+
+        def run():
+            for i in range(self.n_img):
+                lat.extract(self.dimgs[i], ks[i], ds[i])
+            for i in range(self.n_img - 1):
+                o = slice(int(self.first[i]), int(self.first[i] + self.counts[i]))
+                lat.knn(ds[i], ds[i + 1], path=self.path, idx=idx[o], dist=dist[o], accept=acc[o])
+        return run, (desc, idx, dist, acc)
+
+    def same_as(self, outs):
+        d, i, di, a = outs
+        t = self.torch
+        return (t.equal(d, self.desc) and t.equal(i, self.idx) and t.equal(di, self.dist) and
+                t.equal(a, self.acc))
+
+    def close(self):
+        self.plan.close()
+
+
+def roofline_of(kernels, desc_per_launch, pairs_per_launch, workload):
+    """Roofline object of the kernel with the largest time per step."""
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    sec = kd["avg_ms"] * 1e-3
+    if dom in ("knn_batch_fp4", "knn_fp4"):
+        achieved = pairs_per_launch * MATCH_OPS_PER_PAIR / sec / 1e12
+        roof = {"bound": "mfma", "peak": PEAK_FP4_MFMA_TOPS, "unit": "TFLOP/s",
+                "work": "%d pairs x 1,024 ops (FP4 MFMA)" % pairs_per_launch}
+    elif dom in ("knn_batch_mfma", "knn_mfma"):
+        achieved = pairs_per_launch * MATCH_OPS_PER_PAIR / sec / 1e12
+        roof = {"bound": "mfma", "peak": PEAK_INT8_MFMA_TOPS, "unit": "TFLOP/s",
+                "work": "%d pairs x 1,024 ops (int8 MFMA)" % pairs_per_launch}
+    elif dom in ("knn_batch_popcount", "knn_popcount"):
+        achieved = pairs_per_launch * POPCOUNT_OPS_PER_PAIR / sec / 1e12
+        roof = {"bound": "alu", "peak": PEAK_INT_TOPS, "unit": "TFLOP/s",
+                "work": "%d pairs x 32 VALU ops" % pairs_per_launch}
+    else:
+        achieved = desc_per_launch * EXTRACT_OPS_PER_DESC / sec / 1e12
+        roof = {"bound": "alu", "peak": PEAK_VECTOR_TOPS, "unit": "TFLOP/s",
+                "work": "%d descriptors x 100,352 ops" % desc_per_launch,
+                "frac_of_dot4_peak": achieved / PEAK_DOT4_TOPS}
+    roof.update({"kernel": dom, "achieved": achieved, "frac": achieved / roof["peak"],
+                 "avg_ms": kd["avg_ms"], "traffic": recorded_traffic(dom, workload),
+                 "traffic_unit": "bytes/launch"})
+    return roof
+
+
+def cpu_baseline_sfm(imgs, kps, triplets, total_desc, total_pairs, budget_s):
+    """The oracle on a bounded sample of the SfM batch, extrapolated to one
+    whole step: extraction of a keypoint sample of several images, and 2-NN
+    of query samples of several pairs against their whole train image."""
+    import oracle
+    ex_t = ex_n = m_t = m_n = 0.0
+    rounds = 0
+    t_start = time.perf_counter()
+    n_img = len(imgs)
+    while time.perf_counter() - t_start < budget_s and rounds < n_img - 1:
+        i = rounds
+        t0 = time.perf_counter()
+        q, _ = oracle.extract(imgs[i], kps[i][:2500], triplets)
+        t, _ = oracle.extract(imgs[i + 1], kps[i + 1], triplets)
+        ex_t += time.perf_counter() - t0
+        ex_n += len(q) + len(t)
+        t0 = time.perf_counter()
+        oracle.knn(q, t, k=2, ratio=0.8)
+        m_t += time.perf_counter() - t0
+        m_n += len(q) * len(t)
+        rounds += 1
+    cores = oracle.num_threads()
+    ex_rate, m_rate = ex_n / ex_t, m_n / m_t
+    step_s = total_desc / ex_rate + total_pairs / m_rate
+    # The same sample kinds on one thread (a smaller sample).
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    q1, _ = oracle.extract(imgs[0], kps[0][:200], triplets)
+    t1, _ = oracle.extract(imgs[1], kps[1][:2000], triplets)
+    ex1 = 2200 / (time.perf_counter() - t0)
+    t0 = time.perf_counter()
+    oracle.knn(q1, t1, k=2, ratio=0.8)
+    m1 = 200 * 2000 / (time.perf_counter() - t0)
+    oracle.set_threads(cores)
+    return {"value": total_desc / step_s, "unit": "desc/s", "cores": cores, "kind": "oracle",
+            "sample": "%d image pairs: 2,500 query keypoints of image i and all 20,000 of image "
+                      "i + 1 extracted (%d descriptors, %.1f s), then 2-NN of the 2,500 queries "
+                      "against the 20,000 (%.3g pairs, %.1f s); one whole step extrapolated "
+                      "linearly as 1.28 M / extraction rate + 2.52e10 / matching rate"
+                      % (rounds, ex_n, ex_t, m_n, m_t),
+            "extrapolated": True, "extract_desc_per_s": ex_rate, "match_pairs_per_s": m_rate,
+            "pairs_per_s": total_pairs / step_s, "ms_per_step": step_s * 1e3,
+            "value_1_core": total_desc / (total_desc / ex1 + total_pairs / m1),
+            "extract_desc_per_s_1_core": ex1, "match_pairs_per_s_1_core": m1}
+
+
+def hd_component(torch, lat, timer, trip, steps, cpu_seconds):
+    """A 1920x1080 image pair: both images' 10,000 keypoints in one batched
+    extraction, then 10,000 x 10,000 2-NN on every matcher path."""
+    from paper_1609_03986_amd import synth
+    from paper_1609_03986_amd.binding import image_table
+    w = synth.workload_hd()
+    nq, nt = len(w["query_kps"]), len(w["train_kps"])
+    img_q = torch.from_numpy(w["query_image"]).cuda()
+    img_t = torch.from_numpy(w["train_image"]).cuda()
+    kps = torch.from_numpy(np.concatenate([w["query_kps"], w["train_kps"]])).cuda()
+    image_id = torch.from_numpy(np.repeat(np.arange(2, dtype=np.int32), [nq, nt])).cuda()
+    table = image_table([img_q, img_t])
+    desc = torch.empty((nq + nt, 16), dtype=torch.int32, device="cuda")
+    desc_q, desc_t = desc[:nq], desc[nq:]
+    idx = torch.empty((nq, 2), dtype=torch.int32, device="cuda")
+    dist = torch.empty((nq, 2), dtype=torch.int32, device="cuda")
+    acc = torch.empty((nq,), dtype=torch.uint8, device="cuda")
+    for p in ("mfma", "fp4", "popcount", "auto"):
+        lat.reserve(lat.knn_workspace_size(nq, nt, p))
+
+    def extract_both():
+        lat.extract_batch(table, 2, image_id, kps, desc)
+
+    def match(path):
+        lat.knn(desc_q, desc_t, k=2, ratio=0.8, path=path, idx=idx, dist=dist, accept=acc)
+
+    def step():
+        extract_both()
+        match("auto")
+
+    wall, _ = timer.loop(step, steps, 300)
+    _, step_ms = timer.loop(step, steps, 0, per_step=True)
+    kern = kernel_times(lat, torch, step, steps, ("extract", "knn_mfma", "knn_fp4", "knn_popcount",
+                                                  "knn_merge"))
+    ex_wall, _ = timer.loop(extract_both, steps, 2)
     pairs = nq * nt
-    match_rates, match_kernel_ms = {}, {}
+    rates, kms = {}, {}
     for path in ("mfma", "fp4", "popcount"):
-        m_wall, _ = timed_loop(lambda: match(path), args.steps, 2)
-        match_rates[path] = pairs / (m_wall / args.steps)
-        lat.timing(True)
-        for _ in range(args.steps):
-            match(path)
-        torch.cuda.synchronize()
+        m_wall, _ = timer.loop(lambda: match(path), steps, 2)
+        rates[path] = pairs / (m_wall / steps)
         name = {"mfma": "knn_mfma", "fp4": "knn_fp4", "popcount": "knn_popcount"}[path]
-        n, total = lat.timing_read(name)
-        match_kernel_ms[path] = total / max(n, 1)
-        lat.timing(False)
+        kt = kernel_times(lat, torch, lambda: match(path), steps, (name,))
+        kms[path] = kt[name]["avg_ms"]
+    roof = roofline_of(kern, (nq + nt) / kern["extract"]["launches_per_step"], pairs, "hd")
+    out = {"workload": "1920x1080 u8 image pair, 10,000 keypoints each, 10,000 x 10,000 2-NN",
+           "desc_per_s": (nq + nt) / (wall / steps), "ms_per_step": wall / steps * 1e3,
+           "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
+           "extract_desc_per_s": (nq + nt) / (ex_wall / steps),
+           "match_pairs_per_s": rates, "match_kernel_avg_ms": kms, "kernels": kern,
+           "roofline": roof}
+    if cpu_seconds > 0:
+        import oracle
+        t0 = time.perf_counter()
+        oq, _ = oracle.extract(w["query_image"], w["query_kps"], synth.triplet_table())
+        ot, _ = oracle.extract(w["train_image"], w["train_kps"], synth.triplet_table())
+        oracle.knn(oq, ot, k=2, ratio=0.8)
+        out["cpu_oracle_desc_per_s"] = (nq + nt) / (time.perf_counter() - t0)
+    return out, (w, img_q, img_t, kps, image_id, table, desc, torch)
 
-    # --- Keypoint detection (FAST-9, suppression, orientation) of both images,
-    # appended into one array with image ids. ---
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(requested --gpus %d)." % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    comps = set()
+    if args.components != "none":
+        comps = ({"plain", "pcie", "hd", "uneven", "serve", "match_1m", "detect", "weighted",
+                  "dense"}
+                 if args.components == "all" else set(args.components.split(",")))
+
+    import torch
+    from paper_1609_03986_amd import synth
+    from paper_1609_03986_amd.binding import Latch
+
+    torch.cuda.set_device(0)
+    timer = Timer(torch)
+    trip = synth.triplet_table()
+    lat = Latch(trip)
+    tuning = load_tuning(lat)
+
+    # --- The SfM batch and its captured plan. ---
+    log("generating the SfM batch")
+    imgs, kps = synth.sfm_workload()
+    sfm = Batch(torch, lat, imgs, kps, args.path)
+    total, n_pairs = sfm.total, sfm.n_pairs
+    # One run of the plain form and of the plan on the same inputs: the two
+    # must agree (and the GPU leaves its idle clocks before the warm-up).
+    plain_run, plain_out = sfm.per_image_form()
+    plain_run()
+    sfm.run_plan()
+    torch.cuda.synchronize()
+    identical = sfm.same_as(plain_out)
+    flags = lat.check_errors(clear=True)
+
+    log("plan and plain form agree: %s" % identical)
+    # --- The timed region: W untimed steps, then exactly K steps. ---
+    wall, _ = timer.loop(sfm.run_plan, args.steps, args.warmup)
+    ms_per_step = wall / args.steps * 1e3
+    value = total / (wall / args.steps)
+    # Step latency (p50 / p99) from a second run of K steps with an event pair
+    # around each replay.
+    _, step_ms = timer.loop(sfm.run_plan, args.steps, 0, per_step=True)
+    # Kernel durations: the plan's launches as eager calls, with the library's events.
+    kernels = kernel_times(lat, torch, sfm.run_eager, args.steps,
+                           ("extract", "knn_batch_fp4", "knn_batch_mfma", "knn_batch_popcount"))
+    eager_wall, _ = timer.loop(sfm.run_eager, args.steps, 1)
+    roof = roofline_of(kernels, total, n_pairs, "sfm")
+    log("timed %d steps: %.3f ms per step" % (args.steps, ms_per_step))
+
+    components = {"sfm_identical_to_plain_form": bool(identical), "sfm_error_flags": flags,
+                  "sfm_eager_batched_ms_per_step": eager_wall / args.steps * 1e3}
+    if "plain" in comps:
+        p_wall, _ = timer.loop(plain_run, max(3, args.steps // 4), 1)
+        p_ms = p_wall / max(3, args.steps // 4) * 1e3
+        components["sfm_plain_form"] = {"ms_per_step": p_ms, "desc_per_s": total / p_ms * 1e3,
+                                        "plan_speedup": p_ms / ms_per_step}
+    del plain_out, plain_run
+
+    if "pcie" in comps:
+        # The same step with images and keypoints starting in pinned host
+        # memory and descriptors and matches copied back (not the headline).
+        h_imgs = [torch.from_numpy(im).pin_memory() for im in imgs]
+        h_kps = sfm.kp_all.cpu().pin_memory()
+        h_out = [torch.empty(t.shape, dtype=t.dtype, pin_memory=True)
+                 for t in (sfm.desc, sfm.idx, sfm.dist, sfm.acc)]
+
+        def step_pcie():
+            for d, h in zip(sfm.dimgs, h_imgs):
+                d.copy_(h, non_blocking=True)
+            sfm.kp_all.copy_(h_kps, non_blocking=True)
+            sfm.run_plan()
+            for h, d in zip(h_out, (sfm.desc, sfm.idx, sfm.dist, sfm.acc)):
+                h.copy_(d, non_blocking=True)
+
+        pc_wall, _ = timer.loop(step_pcie, max(3, args.steps // 4), 1)
+        components["sfm_pcie_inclusive_desc_per_s"] = total / (pc_wall / max(3, args.steps // 4))
+        del h_imgs, h_out
+
+    cpu = None
+    if args.cpu_seconds > 0:
+        log("oracle baseline")
+        cpu = cpu_baseline_sfm(imgs, kps, trip, total, n_pairs, args.cpu_seconds)
+    sfm.close()
+    del sfm, imgs, kps
+    torch.cuda.empty_cache()
+
+    if "uneven" in comps:
+        log("uneven batch")
+        u_imgs, u_kps = synth.uneven_workload()
+        ub = Batch(torch, lat, u_imgs, u_kps, args.path)
+        u_run, u_out = ub.per_image_form()
+        u_run()
+        ub.run_plan()
+        torch.cuda.synchronize()
+        u_same = ub.same_as(u_out)
+        reps = max(3, args.steps // 2)
+        u_plan, _ = timer.loop(ub.run_plan, reps, 2)
+        u_plain, _ = timer.loop(u_run, reps, 1)
+        components["uneven_batch"] = {
+            "workload": "256 images, sizes uniform over {320x240, 640x480, 1280x720, 1920x1080, "
+                        "4000x3000}, keypoints round(LogNormal(ln 5000, 1)) clipped to "
+                        "[500, 50000], 2-NN over the 255 consecutive pairs",
+            "descriptors": ub.total, "pairs": ub.n_pairs,
+            "plan_ms": u_plan / reps * 1e3, "plain_form_ms": u_plain / reps * 1e3,
+            "plan_speedup": u_plain / u_plan, "plan_desc_per_s": ub.total / (u_plan / reps),
+            "plan_pairs_per_s": ub.n_pairs / (u_plan / reps), "identical": bool(u_same)}
+        ub.close()
+        del ub, u_out, u_run, u_imgs, u_kps
+        torch.cuda.empty_cache()
+
+    hd = None
+    if comps & {"hd", "match_1m", "detect", "weighted", "dense"}:
+        log("1920x1080 pair")
+        hd_out, hd = hd_component(torch, lat, timer, trip, max(args.steps, 200),
+                                  args.cpu_seconds if "hd" in comps else 0)
+        if "hd" in comps:
+            components["image_pair_hd"] = hd_out
+
+    db = None
+    if "serve" in comps:
+        log("serving")
+        components["serving"], db = serving_component(torch, trip)
+    if hd is not None and "match_1m" in comps:
+        log("1,000,000-row database matching")
+        if db is None:
+            from paper_1609_03986_amd import serve
+            db = serve.build_database(lat)
+        components["match_1m"] = match_db_component(torch, lat, hd_desc_q(hd), db)
+    del db
+    torch.cuda.empty_cache()
+
+    log("detection, weighted geometry, dense")
+    if hd is not None and "detect" in comps:
+        components["detection"] = detection_component(torch, lat, timer, hd)
+    if hd is not None and "weighted" in comps:
+        components["weighted_extraction"] = weighted_component(torch, timer, hd)
+    if hd is not None and "dense" in comps:
+        components["dense"] = dense_component(torch, lat, timer, hd)
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "desc/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "images": 64, "descriptors_per_step": total,
+                   "pairs_per_step": n_pairs, "image_pairs": 63, "match_path": args.path,
+                   "parallelism": "single GPU"},
+        "arithmetic": "u8 images, exact int32 patch sums; matching on exact MXFP4 MFMA "
+                      "(0 / +-1 operands, f32 sums of integers < 2^24) unless the tuning "
+                      "table picks int8 MFMA or popcount",
+        "pairs_per_s": n_pairs / (wall / args.steps),
+        "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
+        "tuning": tuning,
+        "kernels": kernels,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paper": PAPER,
+        "components": components,
+        "versions": versions(torch),
+    }
+    print(json.dumps(out), flush=True)
+    lat.close()
+
+
+def serving_component(torch, trip, rates=((50, 200), (200, 400), (800, 400)), slots=4):
+    """A short serving run: Poisson requests of the uneven mix matched against
+    a 1,000,000-row resident database (serve.py runs the full 2,000-request
+    rates)."""
+    from paper_1609_03986_amd import serve
+    from paper_1609_03986_amd.binding import Latch
+    builder = Latch(trip)
+    db = serve.build_database(builder)
+    pool = serve.request_pool()
+    ex = serve.GpuExecutor(db, trip, slots)
+    sched = serve.Scheduler(ex, slots, 8 << 30, db.shape[0])
+    sched.run(serve.max_requests(slots, pool))
+    out = {"db_rows": int(db.shape[0]), "slots": slots, "slot_workspace_bytes": ex.reserved,
+           "rates": []}
+    for qps, n in rates:
+        results, rejected, stats = sched.run(serve.make_requests(n, qps, pool, seed=int(qps)))
+        pairs = sum(len(r.idx) for r in results) * db.shape[0]
+        out["rates"].append({"offered_qps": qps, "requests": n, "served_qps": stats["throughput_rps"],
+                             "p50_ms": stats["p50_ms"], "p99_ms": stats["p99_ms"],
+                             "pairs_per_s": pairs / stats["wall_s"], "rejected": len(rejected),
+                             "max_inflight": stats["max_inflight"]})
+    ex.close()
+    builder.close()
+    return out, db
+
+
+def hd_desc_q(hd):
+    """The 10,000 query descriptors of the 1920x1080 pair."""
+    return hd[6][:10000].clone()
+
+
+def match_db_component(torch, lat, query, db, reps=5):
+    """10,000 queries against the 1,000,000-row database on every matcher path:
+    the split matchers at the serving shape (kernel times from the library's
+    events, including the merge of the train splits)."""
+    nq, nt = query.shape[0], db.shape[0]
+    out = {"nq": nq, "nt": nt, "pairs": nq * nt}
+    for path, names in (("fp4", ("knn_fp4", "knn_merge")), ("mfma", ("knn_mfma", "knn_merge")),
+                        ("popcount", ("knn_popcount", "knn_merge"))):
+        lat.reserve(lat.knn_workspace_size(nq, nt, path))
+        lat.knn(query, db, path=path)
+        kt = kernel_times(lat, torch, lambda: lat.knn(query, db, path=path), reps, names)
+        main_ms = kt[names[0]]["avg_ms"]
+        merge_ms = kt.get("knn_merge", {"ms_per_step": 0.0})["ms_per_step"]
+        peak = {"fp4": PEAK_FP4_MFMA_TOPS, "mfma": PEAK_INT8_MFMA_TOPS, "popcount": PEAK_INT_TOPS}[path]
+        ops = MATCH_OPS_PER_PAIR if path != "popcount" else POPCOUNT_OPS_PER_PAIR
+        achieved = nq * nt * ops / (main_ms * 1e-3) / 1e12
+        out[path] = {"kernel_avg_ms": main_ms, "merge_ms": merge_ms,
+                     "pairs_per_s": nq * nt / ((main_ms + merge_ms) * 1e-3),
+                     "frac_of_peak": achieved / peak, "achieved_tops": achieved}
+    return out
+
+
+def detection_component(torch, lat, timer, hd):
+    """FAST-9 detection, suppression and orientation of both 1920x1080 images,
+    appended into one keypoint array with image ids."""
+    w, img_q, img_t = hd[0], hd[1], hd[2]
     det_cap = 1 << 17
-    det_kps = torch.empty((det_cap, 4), dtype=torch.float32, device=dev)
-    det_ids = torch.empty((det_cap,), dtype=torch.int32, device=dev)
-    det_n = torch.zeros((1,), dtype=torch.int64, device=dev)
+    det_kps = torch.empty((det_cap, 4), dtype=torch.float32, device="cuda")
+    det_ids = torch.empty((det_cap,), dtype=torch.int32, device="cuda")
+    det_n = torch.zeros((1,), dtype=torch.int64, device="cuda")
+    lat.reserve(lat.detect_workspace_size(*img_q.shape))
 
     def detect_both():
         det_n.zero_()
@@ -227,206 +633,101 @@ def main():
         lat.detect(img_t, DETECT_THRESHOLD, det_cap, kps=det_kps, n_kps=det_n, image_id=det_ids,
                    image_index=1)
 
-    d_wall, _ = timed_loop(detect_both, args.steps, 2)
+    steps = 200
+    d_wall, _ = timer.loop(detect_both, steps, 20)
     n_found = int(det_n.item())
-    lat.timing(True)
-    for _ in range(args.steps):
-        detect_both()
-    torch.cuda.synchronize()
-    n_det, det_total = lat.timing_read("detect")
-    lat.timing(False)
-    det_ms = det_total / max(n_det, 1)
+    kt = kernel_times(lat, torch, detect_both, steps, ("detect",))
+    det_ms = kt["detect"]["avg_ms"]
     image_bytes = img_q.numel() + img_t.numel()
     # Algorithmic HBM bytes per image: the image read once, 20 bytes per
     # keypoint written (keypoint and image id).
     det_bytes = (image_bytes + 20 * n_found) / 2
-    detection = {"threshold": DETECT_THRESHOLD, "keypoints_per_step": n_found,
-                 "images_per_s": 2 / (d_wall / args.steps),
-                 "avg_ms_per_image": det_ms,
-                 "roofline": {"bound": "hbm", "achieved": det_bytes / (det_ms * 1e-3) / 1e9,
-                              "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                              "frac": det_bytes / (det_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}}
+    return {"threshold": DETECT_THRESHOLD, "keypoints_per_step": n_found,
+            "images_per_s": 2 / (d_wall / steps), "avg_ms_per_image": det_ms,
+            "roofline": {"bound": "hbm", "achieved": det_bytes / (det_ms * 1e-3) / 1e9,
+                         "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                         "frac": det_bytes / (det_ms * 1e-3) / 1e9 / PEAK_HBM_GBS}}
 
-    # --- The paper's CLATCH geometry: the same 20,000 keypoints extracted
-    # from 64 x 64 windows with 8 x 8 patches and Gaussian integer weights
-    # (one batched launch of the weighted kernel). ---
-    geo_trip = synth.triplet_table_geom(64, 8)
-    geo = Latch(geo_trip, window=64, patch=8, weights=synth.gaussian_weights(8, 2.0, 128))
-    geo_desc = torch.empty_like(desc)
+
+def weighted_component(torch, timer, hd):
+    """The paper's CLATCH geometry: the 20,000 keypoints of the 1920x1080 pair
+    from 64 x 64 windows with 8 x 8 patches and Gaussian integer weights."""
+    from paper_1609_03986_amd import synth
+    from paper_1609_03986_amd.binding import Latch
+    kps, image_id, table = hd[3], hd[4], hd[5]
+    n = kps.shape[0]
+    geo = Latch(synth.triplet_table_geom(64, 8), window=64, patch=8,
+                weights=synth.gaussian_weights(8, 2.0, 128))
+    out_desc = torch.empty((n, 16), dtype=torch.int32, device="cuda")
 
     def extract_geometry():
-        geo.extract_batch(table, 2, image_id, kps, geo_desc)
+        geo.extract_batch(table, 2, image_id, kps, out_desc)
 
-    g_wall, _ = timed_loop(extract_geometry, args.steps, 2)
-    geo.timing(True)
-    for _ in range(args.steps):
-        extract_geometry()
-    torch.cuda.synchronize()
-    n_g, g_total = geo.timing_read("extract")
-    geo.timing(False)
+    steps = 200
+    g_wall, _ = timer.loop(extract_geometry, steps, 20)
+    kt = kernel_times(geo, torch, extract_geometry, steps, ("extract",))
     geo.close()
-    g_ms = g_total / max(n_g, 1)
-    g_ops = (nq + nt) * WEIGHTED_OPS_PER_DESC / (g_ms * 1e-3) / 1e12
-    weighted = {"geometry": "64x64 window, 8x8 patches, Gaussian weights (sigma 2, peak 128)",
-                "desc_per_s": (nq + nt) / (g_wall / args.steps), "avg_ms": g_ms,
-                "roofline": {"bound": "alu", "achieved": g_ops, "peak": PEAK_DOT2_TOPS,
-                             "unit": "TFLOP/s", "frac": g_ops / PEAK_DOT2_TOPS}}
+    g_ms = kt["extract"]["avg_ms"]
+    g_ops = n * WEIGHTED_OPS_PER_DESC / (g_ms * 1e-3) / 1e12
+    return {"geometry": "64x64 window, 8x8 patches, Gaussian weights (sigma 2, peak 128)",
+            "desc_per_s": n / (g_wall / steps), "avg_ms": g_ms,
+            "roofline": {"bound": "alu", "achieved": g_ops, "peak": PEAK_DOT2_TOPS,
+                         "unit": "TFLOP/s", "frac": g_ops / PEAK_DOT2_TOPS}}
 
-    # --- Dense CLATCH (Sec. 6): descriptors at every pixel of both images by
-    # box filters, then windowed 2-NN matching (radius DENSE_RADIUS). ---
-    H_img, W_img = img_q.shape
-    npx = H_img * W_img
-    dq = torch.empty((npx, 16), dtype=torch.int32, device=dev)
-    dt = torch.empty((npx, 16), dtype=torch.int32, device=dev)
+
+def dense_component(torch, lat, timer, hd):
+    """Dense CLATCH (Sec. 6): descriptors at every pixel of both 1920x1080
+    images by box filters, then windowed 2-NN matching (radius DENSE_RADIUS)."""
+    img_q, img_t = hd[1], hd[2]
+    H, W = img_q.shape
+    npx = H * W
+    dq = torch.empty((npx, 16), dtype=torch.int32, device="cuda")
+    dt = torch.empty((npx, 16), dtype=torch.int32, device="cuda")
 
     def dense_both():
-        lat.extract_dense(img_q, 0, 0, W_img, H_img, dq)
-        lat.extract_dense(img_t, 0, 0, W_img, H_img, dt)
+        lat.extract_dense(img_q, 0, 0, W, H, dq)
+        lat.extract_dense(img_t, 0, 0, W, H, dt)
 
-    dense_steps = max(3, min(args.steps // 5, 20))
-    de_wall, _ = timed_loop(dense_both, dense_steps, 1)
-    dm_wall, _ = timed_loop(lambda: lat.knn_window(dq, dt, W_img, H_img, DENSE_RADIUS), dense_steps, 1)
-    lat.timing(True)
-    for _ in range(dense_steps):
-        dense_both()
-        lat.knn_window(dq, dt, W_img, H_img, DENSE_RADIUS)
-    torch.cuda.synchronize()
-    n_de, t_de = lat.timing_read("dense_extract")
-    n_dm, t_dm = lat.timing_read("knn_window")
-    lat.timing(False)
-    de_ms, dm_ms = t_de / max(n_de, 1), t_dm / max(n_dm, 1)
+    def dense_match():
+        lat.knn_window(dq, dt, W, H, DENSE_RADIUS)
+
+    steps = 20
+    de_wall, _ = timer.loop(dense_both, steps, 2)
+    dm_wall, _ = timer.loop(dense_match, steps, 2)
+    ke = kernel_times(lat, torch, dense_both, steps, ("dense_extract",))
+    km = kernel_times(lat, torch, dense_match, steps, ("knn_window",))
+    de_ms, dm_ms = ke["dense_extract"]["avg_ms"], km["knn_window"]["avg_ms"]
     de_ops = npx * DENSE_OPS_PER_PIXEL / (de_ms * 1e-3) / 1e12
     cand = (2 * DENSE_RADIUS + 1) ** 2
-    dm_ops = npx * cand * 32 / (dm_ms * 1e-3) / 1e12
-    dense = {"image": "%dx%d, every pixel" % (W_img, H_img), "radius": DENSE_RADIUS,
-             "desc_per_s": 2 * npx / (de_wall / dense_steps), "extract_avg_ms": de_ms,
-             "match_pairs_per_s": npx * cand / (dm_wall / dense_steps), "match_avg_ms": dm_ms,
-             "extract_roofline": {"bound": "alu", "achieved": de_ops, "peak": PEAK_INT_TOPS,
-                                  "unit": "TFLOP/s", "frac": de_ops / PEAK_INT_TOPS},
-             "match_roofline": {"bound": "alu", "achieved": dm_ops, "peak": PEAK_INT_TOPS,
-                                "unit": "TFLOP/s", "frac": dm_ops / PEAK_INT_TOPS}}
-    del dq, dt
+    dm_ops = npx * cand * POPCOUNT_OPS_PER_PAIR / (dm_ms * 1e-3) / 1e12
+    return {"image": "%dx%d, every pixel" % (W, H), "radius": DENSE_RADIUS,
+            "desc_per_s": 2 * npx / (de_wall / steps), "extract_avg_ms": de_ms,
+            "match_pairs_per_s": npx * cand / (dm_wall / steps), "match_avg_ms": dm_ms,
+            "extract_roofline": {"bound": "alu", "achieved": de_ops, "peak": PEAK_INT_TOPS,
+                                 "unit": "TFLOP/s", "frac": de_ops / PEAK_INT_TOPS,
+                                 "traffic": recorded_traffic("dense_extract", "hd")},
+            "match_roofline": {"bound": "alu", "achieved": dm_ops, "peak": PEAK_INT_TOPS,
+                               "unit": "TFLOP/s", "frac": dm_ops / PEAK_INT_TOPS}}
 
-    # --- The same step with the inputs starting in pinned host memory and the
-    # results copied back (PCIe-inclusive; not the headline value). ---
-    h_img_q = torch.from_numpy(w["query_image"]).pin_memory()
-    h_img_t = torch.from_numpy(w["train_image"]).pin_memory()
-    h_kps_q = torch.from_numpy(w["query_kps"]).pin_memory()
-    h_kps_t = torch.from_numpy(w["train_kps"]).pin_memory()
-    h_idx = torch.empty(idx.shape, dtype=idx.dtype, pin_memory=True)
-    h_dist = torch.empty(dist.shape, dtype=dist.dtype, pin_memory=True)
-    h_acc = torch.empty(acc.shape, dtype=acc.dtype, pin_memory=True)
-    h_desc_q = torch.empty(desc_q.shape, dtype=desc_q.dtype, pin_memory=True)
-    h_desc_t = torch.empty(desc_t.shape, dtype=desc_t.dtype, pin_memory=True)
 
-    def step_pcie():
-        img_q.copy_(h_img_q, non_blocking=True)
-        img_t.copy_(h_img_t, non_blocking=True)
-        kps_q.copy_(h_kps_q, non_blocking=True)
-        kps_t.copy_(h_kps_t, non_blocking=True)
-        step()
-        h_desc_q.copy_(desc_q, non_blocking=True)
-        h_desc_t.copy_(desc_t, non_blocking=True)
-        h_idx.copy_(idx, non_blocking=True)
-        h_dist.copy_(dist, non_blocking=True)
-        h_acc.copy_(acc, non_blocking=True)
-
-    pcie_wall, _ = timed_loop(step_pcie, args.steps, 2)
-    pcie_desc_s = (nq + nt) / (pcie_wall / args.steps)
-
-    # --- Roofline of the dominant kernel of the step. ---
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kd = kernels[dom]
-    if dom in ("knn_mfma", "knn_fp4"):
-        peak = PEAK_INT8_MFMA_TOPS if dom == "knn_mfma" else PEAK_FP4_MFMA_TOPS
-        achieved = pairs * MATCH_OPS_PER_PAIR / (kd["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "mfma", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
-    elif dom == "extract":
-        per_launch = (nq + nt) / kd["launches_per_step"]     # keypoints per extraction launch
-        achieved = per_launch * EXTRACT_OPS_PER_DESC / (kd["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": PEAK_DOT4_TOPS,
-                "unit": "TFLOP/s", "frac": achieved / PEAK_DOT4_TOPS, "traffic": None}
-    else:  # popcount: 16 xor + 16 popcount-accumulate per pair on the VALU
-        peak = CUS * LANES * CLOCK_GHZ / 1000.0
-        achieved = pairs * 32 / (kd["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": dom, "bound": "alu", "achieved": achieved, "peak": peak,
-                "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None}
-
-    roof["traffic"] = recorded_traffic(dom)
-    roof["traffic_unit"] = "bytes/launch"
-
-    # --- CPU oracle baseline: whole steps on the host cores. ---
-    cpu = None
-    if args.cpu_seconds > 0:
-        import oracle
-        reps, t_cpu = 0, 0.0
-        while t_cpu < args.cpu_seconds and reps < 100:
-            t0 = time.perf_counter()
-            oq, _ = oracle.extract(w["query_image"], w["query_kps"], trip)
-            ot, _ = oracle.extract(w["train_image"], w["train_kps"], trip)
-            oracle.knn(oq, ot, k=2, ratio=0.8)
-            t_cpu += time.perf_counter() - t0
-            reps += 1
-        cores = oracle.num_threads()
-        # One whole step on a single thread as well.
-        oracle.set_threads(1)
-        t0 = time.perf_counter()
-        oq, _ = oracle.extract(w["query_image"], w["query_kps"], trip)
-        ot, _ = oracle.extract(w["train_image"], w["train_kps"], trip)
-        oracle.knn(oq, ot, k=2, ratio=0.8)
-        t_one = time.perf_counter() - t0
-        oracle.set_threads(cores)
-        # The oracle on bounded samples of the components, all host cores.
-        def rate(fn, units):
-            t0 = time.perf_counter()
-            fn()
-            return units / (time.perf_counter() - t0)
-        geo_sample = np.concatenate([w["query_kps"], w["train_kps"]])[:2000]
-        comp = {
-            "detection_images_per_s": rate(lambda: oracle.detect(w["query_image"], DETECT_THRESHOLD), 1),
-            "weighted_extraction_desc_per_s": rate(
-                lambda: oracle.extract_geom(w["query_image"], geo_sample, geo_trip, 64, 8,
-                                            synth.gaussian_weights(8, 2.0, 128)), len(geo_sample)),
-            "dense_extraction_desc_per_s": rate(
-                lambda: oracle.extract_dense(w["query_image"], 900, 500, 64, 32, trip), 64 * 32),
-        }
-        dq_s = oracle.extract_dense(w["query_image"], 900, 500, 64, 32, trip)
-        dt_s = oracle.extract_dense(w["train_image"], 900, 500, 64, 32, trip)
-        comp["dense_match_pairs_per_s"] = rate(
-            lambda: oracle.knn_window(dq_s, dt_s, 64, 32, DENSE_RADIUS),
-            sum(min(32, y + DENSE_RADIUS + 1) - max(0, y - DENSE_RADIUS) for y in range(32)) *
-            sum(min(64, x + DENSE_RADIUS + 1) - max(0, x - DENSE_RADIUS) for x in range(64)))
-        cpu = {"value": (nq + nt) * reps / t_cpu, "unit": "desc/s", "cores": cores,
-               "kind": "oracle",
-               "sample": "%d whole steps (2 x 10,000 extractions + 10,000 x 10,000 2-NN) in %.1f s; "
-                         "components: detection of one 1920x1080 image, weighted extraction of "
-                         "2,000 keypoints, dense extraction and radius-%d matching of a 64x32 "
-                         "region" % (reps, t_cpu, DENSE_RADIUS),
-               "value_1_core": (nq + nt) / t_one,
-               "components": comp}
-
-    out = {
-        "metric": METRIC, "value": value, "unit": "desc/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
-        "config": {"workload": WORKLOAD, "descriptors_per_step": nq + nt, "pairs_per_step": pairs,
-                   "match_path": args.path, "parallelism": "single GPU"},
-        "pairs_per_s": pairs / (wall / args.steps),
-        "latency_ms": {"p50": percentile(step_ms, 50), "p99": percentile(step_ms, 99)},
-        "components": {"extract_desc_per_s": extract_desc_s,
-                       "pcie_inclusive_desc_per_s": pcie_desc_s,
-                       "match_pairs_per_s": match_rates,
-                       "match_kernel_avg_ms": match_kernel_ms,
-                       "detection": detection,
-                       "weighted_extraction": weighted,
-                       "dense": dense},
-        "kernels": kernels,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
-    lat.close()
+def versions(torch):
+    """ROCm, HIP runtime, driver and device names for the record."""
+    out = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
+           "device": torch.cuda.get_device_name(0)}
+    try:
+        out["rocm"] = open("/opt/rocm/.info/version").read().strip()
+    except OSError:
+        out["rocm"] = None
+    try:
+        out["amdgpu_driver"] = open("/sys/module/amdgpu/version").read().strip()
+    except OSError:
+        out["amdgpu_driver"] = None
+    try:
+        from paper_1609_03986_amd.binding import latch_version
+        out["library"] = latch_version()
+    except Exception:
+        out["library"] = None
+    return out
 
 
 if __name__ == "__main__":

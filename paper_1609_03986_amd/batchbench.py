@@ -21,37 +21,6 @@ import time
 
 import numpy as np
 
-SIZES = [(240, 320), (480, 640), (720, 1280), (1080, 1920), (3000, 4000)]
-
-
-def sfm_workload(n_img=64, h=2000, w=3000, n_kp=20000, seed=160903986 + 3000):
-    from . import synth
-    g = np.random.default_rng(seed)
-    mosaic = synth.textured_image(g, h + 8 * (n_img - 1), w + 16 * (n_img - 1))
-    imgs = []
-    for i in range(n_img):
-        crop = mosaic[8 * i:8 * i + h, 16 * i:16 * i + w].astype(np.int16)
-        imgs.append(np.clip(crop + g.integers(-4, 5, crop.shape, dtype=np.int16), 0, 255)
-                    .astype(np.uint8))
-    kps = [synth.random_keypoints(g, n_kp, h, w) for _ in range(n_img)]
-    return imgs, kps
-
-
-def uneven_workload(n_img=256, seed=160903986 + 4000, pool_per_size=2):
-    """Pixel data comes from a small seeded pool per size (copied into
-    distinct device buffers by the caller); keypoints are drawn per image."""
-    from . import synth
-    g = np.random.default_rng(seed)
-    pool = {hw: [synth.smoothed_noise(g, *hw) for _ in range(pool_per_size)] for hw in SIZES}
-    imgs, kps = [], []
-    for _ in range(n_img):
-        hw = SIZES[int(g.integers(0, len(SIZES)))]
-        imgs.append(pool[hw][int(g.integers(0, pool_per_size))])
-        n = int(np.clip(np.rint(g.lognormal(np.log(5000), 1.0)), 500, 50000))
-        kps.append(synth.random_keypoints(g, n, *hw))
-    return imgs, kps
-
-
 def run(name, imgs, kps, reps, triplets):
     import torch
     from .binding import Latch, image_table, pair_table
@@ -124,7 +93,7 @@ def main(argv=None):
     trip = synth.triplet_table()
     for name in args.workload:
         t0 = time.perf_counter()
-        imgs, kps = sfm_workload() if name == "sfm" else uneven_workload()
+        imgs, kps = synth.sfm_workload() if name == "sfm" else synth.uneven_workload()
         gen = time.perf_counter() - t0
         out = run(name, imgs, kps, args.reps, trip)
         out["input_generation_s"] = gen

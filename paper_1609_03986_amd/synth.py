@@ -14,6 +14,12 @@ Workloads (stand-ins for the paper's Strecha et al. photogrammetry scenes,
   1 "small":  640x480 smoothed noise, 2,000 upright keypoints on a jittered grid.
   2 "hd":     1920x1080 smoothed noise + rectangles + blobs, 10,000 keypoints with
               angle U[0, 360) and scale 1.2^L, L ~ U{0..7}.
+  3 "sfm":    64 crops of 3000x2000 from one textured mosaic (offsets 16 px / 8 px,
+              +-4 noise), 20,000 keypoints each as in "hd"; the 63 consecutive
+              image pairs are matched.
+  4 "uneven": 256 images, sizes uniform over {320x240, 640x480, 1280x720,
+              1920x1080, 4000x3000}, keypoints per image round(LogNormal(ln 5000, 1))
+              clipped to [500, 50000]; the 255 consecutive pairs are matched.
 """
 import numpy as np
 from scipy.ndimage import gaussian_filter
@@ -183,3 +189,37 @@ def random_descriptors(g, n, p_one=0.5):
     """n random 512-bit descriptors as uint32[n, 16] (bits i.i.d. Bernoulli(p_one))."""
     bits = (g.random((n, 512)) < p_one).astype(np.uint8)
     return np.packbits(bits, axis=1, bitorder="little").view(np.uint32).reshape(n, 16)
+
+
+UNEVEN_SIZES = [(240, 320), (480, 640), (720, 1280), (1080, 1920), (3000, 4000)]
+
+
+def sfm_workload(n_img=64, h=2000, w=3000, n_kp=20000, seed=BASE_SEED + 3000):
+    """Workload 3: n_img crops of h x w from one textured mosaic of
+    (h + 8 (n_img - 1)) x (w + 16 (n_img - 1)), crop i at (16 i, 8 i) plus
+    U{-4..4} noise, and n_kp random keypoints per image.  Returns (images, keypoints)."""
+    g = np.random.default_rng(seed)
+    mosaic = textured_image(g, h + 8 * (n_img - 1), w + 16 * (n_img - 1))
+    imgs = []
+    for i in range(n_img):
+        crop = mosaic[8 * i:8 * i + h, 16 * i:16 * i + w].astype(np.int16)
+        imgs.append(np.clip(crop + g.integers(-4, 5, crop.shape, dtype=np.int16), 0, 255)
+                    .astype(np.uint8))
+    kps = [random_keypoints(g, n_kp, h, w) for _ in range(n_img)]
+    return imgs, kps
+
+
+def uneven_workload(n_img=256, seed=BASE_SEED + 4000, pool_per_size=2):
+    """Workload 4: image sizes uniform over UNEVEN_SIZES, keypoint counts
+    round(LogNormal(ln 5000, 1)) clipped to [500, 50000].  Pixel data comes
+    from a small seeded pool per size (copied into distinct device buffers by
+    the caller); keypoints are drawn per image.  Returns (images, keypoints)."""
+    g = np.random.default_rng(seed)
+    pool = {hw: [smoothed_noise(g, *hw) for _ in range(pool_per_size)] for hw in UNEVEN_SIZES}
+    imgs, kps = [], []
+    for _ in range(n_img):
+        hw = UNEVEN_SIZES[int(g.integers(0, len(UNEVEN_SIZES)))]
+        imgs.append(pool[hw][int(g.integers(0, pool_per_size))])
+        n = int(np.clip(np.rint(g.lognormal(np.log(5000), 1.0)), 500, 50000))
+        kps.append(random_keypoints(g, n, *hw))
+    return imgs, kps
