@@ -432,20 +432,27 @@ int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14);
  * Tuning.  LATCH_PATH_AUTO picks the matcher path from a per-handle table
  * indexed by size buckets, bucket(n) = min(7, floor(log2(max(n, 1)) / 2)),
  * and the split planner of hamming_knn aims at the given number of
- * workgroups per CU.  Defaults: MFMA_FP4 everywhere (batches too), 2 (both
- * MFMA paths) and 8 (popcount) workgroups per CU.  Tuning never changes
- * results, only speed.
+ * workgroups per CU.  The MXFP4 matchers hold 2 or 3 blocks of 32 queries
+ * per wavefront (a workgroup of 4 wavefronts takes 256 or 384 queries
+ * against each staged train tile); the
+ * batched MFMA matchers run the given number of persistent workgroups per
+ * CU.  Defaults: MFMA_FP4 everywhere (batches too), 2 (both MFMA paths) and
+ * 8 (popcount) workgroups per CU, 3 query blocks, 2 batched
+ * workgroups per CU.  Tuning never changes results, only speed.
  */
 typedef struct {
     int8_t path[8][8];               /* [bucket(nq)][bucket(nt)]: LATCH_PATH_MFMA, _POPCOUNT or _MFMA_FP4 */
     int8_t batch_path;               /* path of batched matching under LATCH_PATH_AUTO */
-    int8_t reserved[3];
+    int8_t fp4_query_blocks;         /* 2 or 3 */
+    int8_t reserved[2];              /* 0 */
     int32_t mfma_groups_per_cu;      /* >= 1 */
     int32_t popcount_groups_per_cu;  /* >= 1 */
+    int32_t batch_groups_per_cu;     /* in [1, 8] */
 } latch_tuning;
 
 int latch_get_tuning(latch_handle h, latch_tuning *out);
-/* LATCH_ERANGE if a path entry is not MFMA, POPCOUNT or MFMA_FP4, or a target is < 1. */
+/* LATCH_ERANGE if a path entry is not MFMA, POPCOUNT or MFMA_FP4, a target is < 1,
+ * fp4_query_blocks is not 2 or 3, or batch_groups_per_cu outside [1, 8]. */
 int latch_set_tuning(latch_handle h, const latch_tuning *t);
 
 /*

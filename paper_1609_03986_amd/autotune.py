@@ -1,13 +1,17 @@
 """Autotuner for the matcher: picks, per (query count, train count) size
 bucket, the fastest of the int8-MFMA, MXFP4-MFMA and popcount paths, the
-path for batched matching, and the split planner's workgroups-per-CU target.  It
-measures the library's own kernels (HIP events recorded by the library on
-its launch stream) on random descriptors and caches the result per device
-and library version.
+path for batched matching, the MXFP4 tile shape (2 or 3 blocks of 32
+queries per wavefront), the split planner's workgroups-per-CU target and the
+persistent workgroups per CU of batched matching.  It measures the library's
+own kernels (HIP events recorded by the library on its launch stream) on
+random descriptors and caches the result per device and library version.
 
 Tuning never changes results (every path is exact), only speed.
 
     python -m paper_1609_03986_amd.autotune [--cache PATH] [--quick]
+
+The table the benchmark and the batch and serving drivers load sits in the
+package (tuning.json); `--cache paper_1609_03986_amd/tuning.json` rewrites it.
 """
 import json
 import os
@@ -16,6 +20,7 @@ import sys
 import numpy as np
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "latch_gfx950", "autotune.json")
+IN_TREE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning.json")
 MFMA, POPCOUNT, FP4 = 1, 2, 3
 
 
@@ -64,12 +69,26 @@ def _time_knn(lat, q, t, path, reps):
     return total / reps * 1e-3
 
 
+def _time_batch(lat, desc, pairs, path, reps):
+    import torch
+    out_rows = desc.shape[0]
+    lat.knn_batch(desc, desc, pairs, out_rows, path=path)        # warm-up
+    torch.cuda.synchronize()
+    lat.timing(True)
+    for _ in range(reps):
+        lat.knn_batch(desc, desc, pairs, out_rows, path=path)
+    torch.cuda.synchronize()
+    n, ms = lat.timing_read("knn_batch_" + ("fp4" if path == "fp4" else path))
+    lat.timing(False)
+    return ms / max(n, 1) * 1e-3
+
+
 def tune(lat, buckets=None, reps=5, seed=0, log=None):
     """Measure and install a tuning on the handle `lat` (binding.Latch);
     returns it as a dict."""
     import torch
     from . import synth
-    from .binding import Tuning
+    from .binding import Tuning, pair_table
     g = np.random.default_rng(seed)
     if buckets is None:
         buckets = [(qb, tb) for qb in (2, 4, 6, 7) for tb in (4, 6, 7)]
@@ -90,19 +109,52 @@ def tune(lat, buckets=None, reps=5, seed=0, log=None):
                 (qb, tb, nq, nt, ts[MFMA] * 1e6, ts[FP4] * 1e6, ts[POPCOUNT] * 1e6))
     tuning = dict(base)
     tuning["path"] = fill_table(measured)
-    # Split planner target on the 10,000 x 10,000 shape, for the faster MFMA path there.
+    tuning["batch_path"] = tuning["path"][6][6]
+
+    def trial(**kw):
+        t = dict(tuning, **kw)
+        lat.set_tuning(Tuning.from_dict(t))
+        return t
+
+    # MXFP4 tile shape: the split matcher at 10,000 x 10,000 plus the batched
+    # matcher on a batch shaped like structure from motion (64 images of
+    # 20,000 descriptors, the 63 consecutive pairs; random bits).
     q, t = pool[:10000], pool[rows - 10000:] if rows >= 20000 else pool[:10000]
+    bsize, bsets = 20000, 64
+    bdesc = torch.from_numpy(g.integers(0, 2 ** 32, size=(bsize * bsets, 16), dtype=np.uint32)
+                             .view(np.int32)).cuda()
+    bpairs = pair_table([(i * bsize, bsize, (i + 1) * bsize, bsize, i * bsize)
+                         for i in range(bsets - 1)])
+    lat.reserve(lat.knn_batch_workspace_size(bsets - 1, bsize * bsets))
+    shapes = {}
+    for qb in (2, 3):
+        trial(fp4_query_blocks=qb)
+        shapes[qb] = (_time_knn(lat, q, t, "fp4", reps) +
+                      _time_batch(lat, bdesc, bpairs, "fp4", reps))
+    tuning["fp4_query_blocks"] = choose(shapes)
+    if log:
+        log("fp4 query blocks: %s -> %d" % ({k: round(v * 1e6, 1) for k, v in shapes.items()},
+                                             tuning["fp4_query_blocks"]))
+    # Split planner target on the 10,000 x 10,000 shape, for the faster MFMA path there.
     mfma_path = "fp4" if tuning["path"][6][6] == FP4 else "mfma"
     targets = {}
     for w in (1, 2, 3, 4):
-        trial = dict(tuning, mfma_groups_per_cu=w)
-        lat.set_tuning(Tuning.from_dict(trial))
+        trial(mfma_groups_per_cu=w)
         targets[w] = _time_knn(lat, q, t, mfma_path, reps)
     tuning["mfma_groups_per_cu"] = choose(targets)
     if log:
         log("mfma workgroups per CU: %s -> %d" %
             ({w: round(v * 1e6, 1) for w, v in targets.items()}, tuning["mfma_groups_per_cu"]))
-    tuning["batch_path"] = tuning["path"][6][6]
+    # Persistent workgroups per CU of batched matching.
+    bpath = {FP4: "fp4", MFMA: "mfma", POPCOUNT: "popcount"}[tuning["batch_path"]]
+    groups = {}
+    for w in (1, 2, 3, 4):
+        trial(batch_groups_per_cu=w)
+        groups[w] = _time_batch(lat, bdesc, bpairs, bpath, reps)
+    tuning["batch_groups_per_cu"] = choose(groups)
+    if log:
+        log("batch workgroups per CU: %s -> %d" %
+            ({w: round(v * 1e6, 1) for w, v in groups.items()}, tuning["batch_groups_per_cu"]))
     lat.set_tuning(Tuning.from_dict(tuning))
     return tuning
 

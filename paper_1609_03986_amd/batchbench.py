@@ -24,7 +24,9 @@ import numpy as np
 def run(name, imgs, kps, reps, triplets):
     import torch
     from .binding import Latch, image_table, pair_table
+    from . import autotune
     lat = Latch(triplets)
+    tuned = autotune.load(lat, autotune.IN_TREE)
     dimgs = [torch.from_numpy(im).cuda() for im in imgs]
     counts = [len(k) for k in kps]
     first = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
@@ -81,7 +83,8 @@ def run(name, imgs, kps, reps, triplets):
             "per_image_ms": t_a * 1e3, "batched_graph_ms": t_b * 1e3,
             "speedup": t_a / t_b, "batched_desc_per_s": total / t_b,
             "batched_pairs_per_s": n_pairs_total / t_b, "identical": bool(same),
-            "error_flags": flags}
+            "error_flags": flags,
+            "tuning": "in-tree table" if tuned is not None else "library default"}
 
 
 def main(argv=None):

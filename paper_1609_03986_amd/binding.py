@@ -427,24 +427,29 @@ def hamming_knn_batch(h, query, train, pairs, out_rows, k=2, ratio=0.8, path="au
 class Tuning(ctypes.Structure):
     """latch_tuning: path per (bucket(nq), bucket(nt)), batch path, split targets."""
     _fields_ = [("path", (ctypes.c_int8 * 8) * 8), ("batch_path", ctypes.c_int8),
-                ("reserved", ctypes.c_int8 * 3), ("mfma_groups_per_cu", ctypes.c_int32),
-                ("popcount_groups_per_cu", ctypes.c_int32)]
+                ("fp4_query_blocks", ctypes.c_int8), ("reserved", ctypes.c_int8 * 2),
+                ("mfma_groups_per_cu", ctypes.c_int32),
+                ("popcount_groups_per_cu", ctypes.c_int32), ("batch_groups_per_cu", ctypes.c_int32)]
+
+    SCALARS = ("batch_path", "fp4_query_blocks", "mfma_groups_per_cu", "popcount_groups_per_cu",
+               "batch_groups_per_cu")
+    DEFAULTS = {"fp4_query_blocks": 3, "batch_groups_per_cu": 2}
 
     def to_dict(self):
-        return {"path": [[int(self.path[i][j]) for j in range(8)] for i in range(8)],
-                "batch_path": int(self.batch_path),
-                "mfma_groups_per_cu": int(self.mfma_groups_per_cu),
-                "popcount_groups_per_cu": int(self.popcount_groups_per_cu)}
+        d = {"path": [[int(self.path[i][j]) for j in range(8)] for i in range(8)]}
+        d.update({k: int(getattr(self, k)) for k in self.SCALARS})
+        return d
 
     @classmethod
     def from_dict(cls, d):
+        """A latch_tuning from a dict; fields missing from older tables take
+        the library defaults."""
         t = cls()
         for i in range(8):
             for j in range(8):
                 t.path[i][j] = d["path"][i][j]
-        t.batch_path = d["batch_path"]
-        t.mfma_groups_per_cu = d["mfma_groups_per_cu"]
-        t.popcount_groups_per_cu = d["popcount_groups_per_cu"]
+        for k in cls.SCALARS:
+            setattr(t, k, d.get(k, cls.DEFAULTS.get(k, 0)))
         return t
 
 

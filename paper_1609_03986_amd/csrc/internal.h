@@ -150,8 +150,16 @@ struct KnnPlan {
 // Which matcher kernel runs.
 enum class SplitKernel { kMfmaI8, kMfmaFp4, kPopcount };
 
+// Tile shapes and selection variants of the MFMA matchers (from the tuning
+// table; none changes results).
+struct KnnShape {
+    int fp4_query_blocks = 3;       // 32-query blocks per wavefront of the MXFP4 kernels: 2 or 3
+    int batch_groups_per_cu = 2;    // persistent workgroups per CU of the batched MFMA matchers
+};
+
 struct KnnSplitArgs {
     const uint32_t *query, *train;
+    KnnShape shape;
     KnnPlan plan;
     uint64_t *partial;
     int k;
@@ -161,9 +169,11 @@ struct KnnSplitArgs {
 };
 
 constexpr int64_t kFp4MaxSplitRows = 1 << 14;    // MXFP4 keys hold a 14-bit split-local index
-constexpr int kFp4QueriesPerGroup = 256;         // queries per MXFP4 workgroup (64 per wavefront)
+constexpr int kMfmaWaves = 4;                    // wavefronts per MFMA matcher workgroup
 
 hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_t stream);
+// Queries per workgroup of a matcher kernel (the unit of query groups and batch items).
+int queries_per_group(SplitKernel which, const KnnShape &shape);
 hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream);
 
 // Layout-compatible with latch_pair of the C ABI.
@@ -201,6 +211,7 @@ struct BatchArgs {
     uint32_t *flags;
     int num_cus;
     SplitKernel kind;
+    KnnShape shape;
 };
 
 hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream);

@@ -36,6 +36,7 @@ __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
     return max(min(a, b), min(max(a, b), c));
 }
 
+
 // Four bits -> four bytes of value 0/1 (bit e of nib -> byte e).  The four
 // shifted copies of nib occupy disjoint bit ranges, so the product has no
 // carries; nib < 16 and the constant < 2^24 make it a full-rate 24-bit multiply.
@@ -85,7 +86,6 @@ __device__ __forceinline__ v4i expand16(uint32_t x)
 // each lane keeps a running top-2 for one query; lanes l and l ^ 32 merge at
 // the end.
 // ---------------------------------------------------------------------------
-constexpr int kMfmaWaves = 4;
 constexpr int kMfmaThreads = kMfmaWaves * 64;
 constexpr int kQueryBlocks = 2;                        // 32-query blocks per wavefront
 constexpr int kQueriesPerWave = 32 * kQueryBlocks;
@@ -113,9 +113,12 @@ __device__ __forceinline__ v4i expand16_pm1(uint32_t x)
 __device__ __forceinline__ uint2 load_tile(const uint32_t *__restrict__ train, int nt, int tile,
                                            int tid)
 {
+    // Rows past nt load row nt - 1 (or row 0 of an empty set, which is never
+    // staged) and are zeroed, without a branch.
     const int row = tile * kTileRows + (tid & 31);
-    return row < nt ? reinterpret_cast<const uint2 *>(train + (size_t)row * kWords)[tid >> 5]
-                    : make_uint2(0, 0);
+    const int src = max(min(row, nt - 1), 0);
+    const uint2 w = reinterpret_cast<const uint2 *>(train + (size_t)src * kWords)[tid >> 5];
+    return row < nt ? w : make_uint2(0, 0);
 }
 
 __device__ __forceinline__ void stage_tile(uint2 w, int tid, v4i *__restrict__ buf)
@@ -354,6 +357,12 @@ __device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c
 // K = 64 s + 32 (l / 32) + e are packed word 2 s + l / 32 of that row, bit e
 // -> nibble e (16 bytes).  Queries use the same map.  Bytes expand to FP4
 // through a 256-entry table in LDS (byte -> 8 nibbles).
+//
+// Tile shape.  A wavefront holds QB blocks of 32 queries (QB = 2 or 3, from
+// the tuning table), so each train fragment read from LDS feeds QB MFMAs and
+// each staged tile serves 128 QB queries of the workgroup.  Measured on the
+// SfM batch (63 pairs of 20k x 20k): 5.0 ms per batched launch at QB = 2,
+// 4.76 ms at QB = 3 (whose 256 VGPRs hold 96 of query fragments).
 // ---------------------------------------------------------------------------
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -363,9 +372,6 @@ constexpr int kFp4TileVec = kFp4Steps * 64;           // 16-byte fragments per t
 constexpr int kFp4ScaleTrain = 127;                   // E8M0 2^0
 constexpr int kFp4ScaleQuery = 127 + 14;              // E8M0 2^14
 constexpr float kFp4None = -33554432.0f;              // -2^25
-// Query blocks of 32 per wavefront: each train fragment read from LDS feeds
-// this many MFMAs.
-constexpr int kFp4QueryBlocks = kFp4QueriesPerGroup / (kMfmaWaves * 32);
 
 // Byte -> 8 FP4 nibbles (bit e -> nibble e): `one` for a set bit, `zero` for a clear one.
 __device__ __forceinline__ uint32_t fp4_byte(uint32_t byte, uint32_t one, uint32_t zero)
@@ -381,13 +387,16 @@ __device__ __forceinline__ uint4 fp4_word(uint32_t w, const uint32_t *__restrict
     return make_uint4(lut[w & 0xffu], lut[(w >> 8) & 0xffu], lut[(w >> 16) & 0xffu], lut[w >> 24]);
 }
 
-// Maximum of two finite floats as one v_max_f32 (the IEEE-mode fmaxf adds
-// a NaN-quieting instruction per operand; keys are never NaN).
-__device__ __forceinline__ float max_key(float a, float b)
+// Insert one key into a running top two (k1 >= k2): k2 = med3(k1, k2, key),
+// then k1 = max(k1, key), as one unit, so that only the current k1 is ever
+// live (the independent chains of the query blocks interleave; v_max_f32
+// written out, since the IEEE-mode fmaxf adds NaN quieting per operand).
+__device__ __forceinline__ void insert_key(float &k1, float &k2, float key)
 {
-    float r;
-    asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
-    return r;
+    asm("v_med3_f32 %1, %0, %1, %2\n\t"
+        "v_max_f32 %0, %0, %2"
+        : "+v"(k1), "+v"(k2)
+        : "v"(key));
 }
 
 __device__ __forceinline__ v8i fp4_operand(uint4 f)
@@ -470,9 +479,8 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     if (t_begin < t_end) stage_tile_fp4(ld0, tid, lut_train, tbuf[0]);
     __syncthreads();
 
-    // One tile: MFMAs over LDS buffer `buf`, then the top-2 update.
-    auto tile_step = [&](int tile, int buf) {
-        v16f acc[QB];
+    // The MFMAs of one tile over LDS buffer `buf`.
+    auto tile_mfma = [&](int buf, v16f (&acc)[QB]) {
 #pragma unroll
         for (int s = 0; s < kFp4Steps; ++s) {
             const v8i a = fp4_operand(tbuf[buf][s * 64 + lane]);
@@ -482,7 +490,24 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
                     a, fp4_operand(bq[qb][s]), s == 0 ? c0 : acc[qb], 4, 4, 0, kFp4ScaleTrain, 0,
                     kFp4ScaleQuery);
         }
-        const int valid_rows = nt - tile * kTileRows;        // < 32 only in the last tile
+    };
+    // The top-2 update with one tile's keys: the running top two move into
+    // this tile's frame, then take the tile's 16 keys per query block.
+    auto tile_top2 = [&](const v16f (&acc)[QB]) {
+#pragma unroll
+        for (int qb = 0; qb < QB; ++qb) {
+            k1[qb] += 32.0f;
+            k2[qb] += 32.0f;
+        }
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+#pragma unroll
+            for (int qb = 0; qb < QB; ++qb) insert_key(k1[qb], k2[qb], acc[qb][r]);
+        }
+    };
+    // Rows past nt (in the last tile only) take a key below every real one.
+    auto mask_tail = [&](int tile, v16f (&acc)[QB]) {
+        const int valid_rows = nt - tile * kTileRows;
         if (valid_rows < kTileRows) {
 #pragma unroll
             for (int r = 0; r < 16; ++r)
@@ -490,24 +515,16 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
 #pragma unroll
                     for (int qb = 0; qb < QB; ++qb) acc[qb][r] = kFp4None;
         }
-        // Move the running top-2 into this tile's frame, then update it.
-#pragma unroll
-        for (int qb = 0; qb < QB; ++qb) {
-            if (tile != t_begin) {
-                k1[qb] += 32.0f;
-                k2[qb] += 32.0f;
-            }
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const float key = acc[qb][r];
-                k2[qb] = __builtin_amdgcn_fmed3f(k1[qb], k2[qb], key);
-                k1[qb] = max_key(k1[qb], key);
-            }
-        }
-
+    };
+    auto tile_step = [&](int tile, int buf) {
+        v16f acc[QB];
+        tile_mfma(buf, acc);
+        mask_tail(tile, acc);
+        tile_top2(acc);
     };
 
-    // Straight-line body, as in the int8 path.
+    // Straight-line body, as in the int8 path.  (The first update moves the
+    // empty keys up by 32 too, which keeps them below -2^24.)
     for (int tile = t_begin; tile < t_end; tile += 2) {
         tile_step(tile, 0);
         stage_tile_fp4(ra, tid, lut_train, tbuf[1]);
@@ -674,6 +691,7 @@ knn_mfma_kernel(SplitArgs a)
               a.nsplit == 1 ? direct : part, tbuf);
 }
 
+template <int QB>
 __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 knn_fp4_kernel(SplitArgs a)
 {
@@ -684,10 +702,10 @@ knn_fp4_kernel(SplitArgs a)
     __syncthreads();
     const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
     const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
-    uint64_t best[kFp4QueryBlocks][2];
+    uint64_t best[QB][2];
     fp4_init_best(best);
-    fp4_item<kFp4QueryBlocks>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows,
-                              best, tbuf, lut_train, lut_query);
+    fp4_item<QB>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows, best, tbuf,
+                 lut_train, lut_query);
     fp4_store(best, a.nq, a.nt, blockIdx.x, blockIdx.y, a.nsplit == 1 ? direct : part);
 }
 
@@ -710,7 +728,7 @@ __global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void knn_batch_setup_kernel(
     const PairEntry *__restrict__ pairs, int n_pairs, int64_t query_rows, int64_t train_rows,
-    int64_t out_rows, int64_t item_capacity, PairInfo *__restrict__ info,
+    int64_t out_rows, int64_t item_capacity, int group, PairInfo *__restrict__ info,
     BatchState *__restrict__ st, uint32_t *__restrict__ flags)
 {
     __shared__ int64_t part[256];
@@ -726,7 +744,7 @@ __global__ __launch_bounds__(256) void knn_batch_setup_kernel(
                         (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
                         e.out_first >= 0 && e.out_first + e.nq <= out_rows;
         bad |= !ok;
-        local += ok ? (e.nq + 255) / 256 : 0;
+        local += ok ? (e.nq + group - 1) / group : 0;
     }
     part[tid] = local;
     __syncthreads();
@@ -747,7 +765,7 @@ __global__ __launch_bounds__(256) void knn_batch_setup_kernel(
                         e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
                         (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
                         e.out_first >= 0 && e.out_first + e.nq <= out_rows;
-        const int64_t groups = ok && !overflow ? (e.nq + 255) / 256 : 0;
+        const int64_t groups = ok && !overflow ? (e.nq + group - 1) / group : 0;
         info[p].item_first = first;
         info[p].qgroups = (int32_t)groups;
         info[p].valid = ok && !overflow;
@@ -785,7 +803,7 @@ __device__ __forceinline__ int64_t claim_item(BatchState *__restrict__ st, int *
 
 enum class BatchKind { kPopcount, kMfmaI8, kMfmaFp4 };
 
-template <BatchKind kKind>
+template <BatchKind kKind, int QB>
 __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
                                            const uint32_t *__restrict__ train,
                                            const PairEntry *__restrict__ pairs,
@@ -812,13 +830,12 @@ __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
         if constexpr (kKind == BatchKind::kMfmaFp4) {
             // The pair's whole train range in ranges of at most 2^14 rows
             // (the MXFP4 keys' index field), merged in registers.
-            uint64_t best[kFp4QueryBlocks][2];
+            uint64_t best[QB][2];
             fp4_init_best(best);
             const int ranges = max(1, (nt + (int)kFp4MaxSplitRows - 1) / (int)kFp4MaxSplitRows);
             for (int r = 0; r < ranges; ++r)
-                fp4_item<kFp4QueryBlocks>(q, (int)e.nq, t, nt, qgroup, r, (int)kFp4MaxSplitRows, best,
-                                          reinterpret_cast<uint4 (*)[kFp4TileVec]>(tbuf), lut_train,
-                                          lut_query);
+                fp4_item<QB>(q, (int)e.nq, t, nt, qgroup, r, (int)kFp4MaxSplitRows, best,
+                             reinterpret_cast<uint4 (*)[kFp4TileVec]>(tbuf), lut_train, lut_query);
             fp4_store(best, (int)e.nq, nt, qgroup, 0, out);
         } else {
             const int split_rows = max(kTileRows, (nt + kTileRows - 1) / kTileRows * kTileRows);
@@ -841,10 +858,12 @@ knn_batch_mfma_kernel(const uint32_t *__restrict__ query, const uint32_t *__rest
 {
     __shared__ v4i tbuf[2][kTileVec];
     __shared__ int slot;
-    batch_loop<BatchKind::kMfmaI8>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
-                                   accept, tbuf, nullptr, nullptr, &slot, n_pairs);
+    batch_loop<BatchKind::kMfmaI8, kQueryBlocks>(query, train, pairs, info, item_pair, st, k, ratio,
+                                                 idx, dist, accept, tbuf, nullptr, nullptr, &slot,
+                                                 n_pairs);
 }
 
+template <int QB>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void
 knn_batch_fp4_kernel(const uint32_t *__restrict__ query, const uint32_t *__restrict__ train,
                      const PairEntry *__restrict__ pairs, int n_pairs,
@@ -858,8 +877,8 @@ knn_batch_fp4_kernel(const uint32_t *__restrict__ query, const uint32_t *__restr
     lut_train[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0x0u);
     lut_query[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0xau);
     __syncthreads();
-    batch_loop<BatchKind::kMfmaFp4>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
-                                    accept, tbuf, lut_train, lut_query, &slot, n_pairs);
+    batch_loop<BatchKind::kMfmaFp4, QB>(query, train, pairs, info, item_pair, st, k, ratio, idx,
+                                        dist, accept, tbuf, lut_train, lut_query, &slot, n_pairs);
 }
 
 __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
@@ -869,23 +888,30 @@ __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
     int32_t *__restrict__ idx, int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
 {
     __shared__ int slot;
-    batch_loop<BatchKind::kPopcount>(query, train, pairs, info, item_pair, st, k, ratio, idx, dist,
-                                     accept, nullptr, nullptr, nullptr, &slot, n_pairs);
+    batch_loop<BatchKind::kPopcount, 1>(query, train, pairs, info, item_pair, st, k, ratio, idx,
+                                        dist, accept, nullptr, nullptr, nullptr, &slot, n_pairs);
 }
 
 }  // namespace
+
+int queries_per_group(SplitKernel which, const KnnShape &shape)
+{
+    return which == SplitKernel::kMfmaFp4 ? kMfmaWaves * 32 * shape.fp4_query_blocks : 256;
+}
 
 hipError_t launch_knn_split(const KnnSplitArgs &a, SplitKernel which, hipStream_t stream)
 {
     const SplitArgs k{a.query, a.train, (int)a.plan.nq, (int)a.plan.nt, (int)a.plan.split_rows,
                       a.plan.nsplit, a.partial, a.k, a.ratio, a.idx, a.dist, a.accept};
-    const int64_t group = which == SplitKernel::kMfmaFp4 ? kFp4QueriesPerGroup : 256;
+    const int64_t group = queries_per_group(which, a.shape);
     const int64_t qgroups = (a.plan.nq + group - 1) / group;
     const dim3 grid((unsigned)qgroups, (unsigned)a.plan.nsplit);
     if (which == SplitKernel::kMfmaI8)
         hipLaunchKernelGGL(knn_mfma_kernel, grid, dim3(kMfmaThreads), 0, stream, k);
+    else if (which == SplitKernel::kMfmaFp4 && a.shape.fp4_query_blocks == 3)
+        hipLaunchKernelGGL(knn_fp4_kernel<3>, grid, dim3(kMfmaThreads), 0, stream, k);
     else if (which == SplitKernel::kMfmaFp4)
-        hipLaunchKernelGGL(knn_fp4_kernel, grid, dim3(kMfmaThreads), 0, stream, k);
+        hipLaunchKernelGGL(knn_fp4_kernel<2>, grid, dim3(kMfmaThreads), 0, stream, k);
     else
         hipLaunchKernelGGL(knn_popcount_kernel, grid, dim3(256), 0, stream, k);
     return hipGetLastError();
@@ -904,21 +930,26 @@ hipError_t launch_knn_merge(const KnnSplitArgs &a, hipStream_t stream)
 hipError_t launch_knn_batch(const BatchArgs &a, hipStream_t stream)
 {
     hipLaunchKernelGGL(knn_batch_setup_kernel, dim3(1), dim3(256), 0, stream, a.pairs, a.n_pairs,
-                       a.query_rows, a.train_rows, a.out_rows, a.item_capacity, a.info, a.state,
-                       a.flags);
+                       a.query_rows, a.train_rows, a.out_rows, a.item_capacity,
+                       queries_per_group(a.kind, a.shape), a.info, a.state, a.flags);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     const int fill_blocks = a.n_pairs < 4096 ? a.n_pairs : 4096;
     hipLaunchKernelGGL(knn_batch_fill_kernel, dim3(fill_blocks), dim3(256), 0, stream, a.info,
                        a.n_pairs, a.item_pair);
     if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int blocks = a.num_cus * (a.kind == SplitKernel::kPopcount ? 8 : 2);
+    const int blocks =
+        a.num_cus * (a.kind == SplitKernel::kPopcount ? 8 : a.shape.batch_groups_per_cu);
     if (a.kind == SplitKernel::kMfmaI8)
         hipLaunchKernelGGL(knn_batch_mfma_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
                            a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
                            a.idx, a.dist, a.accept);
+    else if (a.kind == SplitKernel::kMfmaFp4 && a.shape.fp4_query_blocks == 3)
+        hipLaunchKernelGGL(knn_batch_fp4_kernel<3>, dim3(blocks), dim3(256), 0, stream, a.query,
+                           a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
+                           a.idx, a.dist, a.accept);
     else if (a.kind == SplitKernel::kMfmaFp4)
-        hipLaunchKernelGGL(knn_batch_fp4_kernel, dim3(blocks), dim3(256), 0, stream, a.query,
+        hipLaunchKernelGGL(knn_batch_fp4_kernel<2>, dim3(blocks), dim3(256), 0, stream, a.query,
                            a.train, a.pairs, a.n_pairs, a.info, a.item_pair, a.state, a.k, a.ratio,
                            a.idx, a.dist, a.accept);
     else

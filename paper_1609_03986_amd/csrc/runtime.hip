@@ -309,8 +309,25 @@ void default_tuning(latch_tuning *t)
     std::memset(t, 0, sizeof *t);
     std::memset(t->path, LATCH_PATH_MFMA_FP4, sizeof t->path);
     t->batch_path = LATCH_PATH_MFMA_FP4;
+    t->fp4_query_blocks = 3;
     t->mfma_groups_per_cu = 2;
     t->popcount_groups_per_cu = 8;
+    t->batch_groups_per_cu = 2;
+}
+
+KnnShape knn_shape(const latch_tuning &t)
+{
+    KnnShape s;
+    s.fp4_query_blocks = t.fp4_query_blocks;
+    s.batch_groups_per_cu = t.batch_groups_per_cu;
+    return s;
+}
+
+SplitKernel split_kernel(int path)
+{
+    return path == LATCH_PATH_MFMA       ? SplitKernel::kMfmaI8
+           : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
+                                         : SplitKernel::kPopcount;
 }
 
 KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuning &tune)
@@ -324,7 +341,7 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
         p.split_rows = kTileRows;
         return p;
     }
-    const int64_t group = path == LATCH_PATH_MFMA_FP4 ? kFp4QueriesPerGroup : 256;
+    const int64_t group = queries_per_group(split_kernel(path), knn_shape(tune));
     const int64_t qgroups = (nq + group - 1) / group;
     const int64_t slots = (int64_t)num_cus * (path == LATCH_PATH_POPCOUNT ? tune.popcount_groups_per_cu
                                                                         : tune.mfma_groups_per_cu);
@@ -401,9 +418,8 @@ BatchArgs batch_args(latch_handle h, uint8_t *ws, const uint32_t *query_dev, int
     a.accept = accept_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
-    a.kind = path == LATCH_PATH_POPCOUNT ? SplitKernel::kPopcount
-             : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
-                                           : SplitKernel::kMfmaI8;
+    a.kind = split_kernel(path);
+    a.shape = knn_shape(h->tuning);
     return a;
 }
 
@@ -519,6 +535,7 @@ int knn_call(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32
     KnnSplitArgs a;
     a.query = query_dev;
     a.train = train_dev;
+    a.shape = knn_shape(h->tuning);
     a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
     a.partial = nullptr;
     a.k = k;
@@ -543,9 +560,7 @@ int knn_call(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32
             a.partial = reinterpret_cast<uint64_t *>(h->ws);
         }
     }
-    const SplitKernel which = path == LATCH_PATH_MFMA       ? SplitKernel::kMfmaI8
-                              : path == LATCH_PATH_MFMA_FP4 ? SplitKernel::kMfmaFp4
-                                                            : SplitKernel::kPopcount;
+    const SplitKernel which = split_kernel(path);
     const char *name = which == SplitKernel::kMfmaI8    ? "knn_mfma"
                        : which == SplitKernel::kMfmaFp4 ? "knn_fp4"
                                                         : "knn_popcount";
@@ -573,7 +588,7 @@ struct latch_plan_ctx {
 
 extern "C" {
 
-const char *latch_version(void) { return "latch-gfx950 0.1"; }
+const char *latch_version(void) { return "latch-gfx950 0.2"; }
 
 int latch_rotation_table(int16_t *cos_q14, int16_t *sin_q14)
 {
@@ -977,6 +992,12 @@ int latch_set_tuning(latch_handle h, const latch_tuning *t)
     if (!ok_path(t->batch_path)) return fail(h, LATCH_ERANGE, "tuning batch_path");
     if (t->mfma_groups_per_cu < 1 || t->popcount_groups_per_cu < 1)
         return fail(h, LATCH_ERANGE, "tuning workgroup targets must be >= 1");
+    if (t->fp4_query_blocks != 2 && t->fp4_query_blocks != 3)
+        return fail(h, LATCH_ERANGE, "tuning fp4_query_blocks = %d (must be 2 or 3)",
+                    t->fp4_query_blocks);
+    if (t->batch_groups_per_cu < 1 || t->batch_groups_per_cu > 8)
+        return fail(h, LATCH_ERANGE, "tuning batch_groups_per_cu = %d (must be in [1, 8])",
+                    t->batch_groups_per_cu);
     h->tuning = *t;
     return LATCH_OK;
 }

@@ -178,6 +178,7 @@ class GpuExecutor:
 
     def __init__(self, db, triplets, n_slots, ratio=0.8, path="auto", max_kps=50000):
         import torch
+        from . import autotune
         from .binding import Latch
         self.torch = torch
         self.db = db
@@ -186,6 +187,7 @@ class GpuExecutor:
         self.slots = []
         for _ in range(n_slots):
             lat = Latch(triplets)
+            self.tuning = autotune.load(lat, autotune.IN_TREE)
             self.slots.append({"stream": torch.cuda.Stream(), "lat": lat, "event": None,
                                "out": None})
         self.reserved = self.largest_workspace(max_kps)
@@ -198,9 +200,10 @@ class GpuExecutor:
 
     def largest_workspace(self, max_kps):
         """The largest need of any request of 1 .. max_kps keypoints.  The need
-        grows with the query count while the number of 256-query groups stays
-        fixed, so the largest of each group count is at its last count."""
-        counts = sorted({min(max_kps, 256 * g) for g in range(1, -(-max_kps // 256) + 1)})
+        grows with the query count while the number of query groups (256 or
+        384 queries, multiples of 128) stays fixed, so the largest of each
+        group count is at a multiple of 128 or at max_kps."""
+        counts = sorted({min(max_kps, 128 * g) for g in range(1, -(-max_kps // 128) + 1)})
         return max(self.workspace_need(n) for n in counts)
 
     def workspace_bytes(self, n_kps):
@@ -334,6 +337,7 @@ def main(argv=None):
         stats.update({"offered_qps": qps, "db_rows": args.db_rows, "slots": args.slots,
                       "pairs_per_s": pairs / stats["wall_s"], "path": args.path,
                       "slot_workspace_bytes": ex.reserved,
+                      "tuning": "in-tree table" if ex.tuning is not None else "library default",
                       "timed_out": len(stats["timed_out"]), "cancelled": len(stats["cancelled"])})
         print(json.dumps(stats), flush=True)
     ex.close()
