@@ -147,8 +147,8 @@ __device__ __forceinline__ void offsets(const Keypoint &k, int uv, int &ox, int 
 {
     const int u = (int)(short)(uv & 0xffff);
     const int v = uv >> 16;
-    ox = round_q22(mul_i24(mad_i24(k.c, u, mul_i24(-k.s, v)), k.sq));
-    oy = round_q22(mul_i24(mad_i24(k.s, u, mul_i24(k.c, v)), k.sq));
+    ox = round_q22(mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))));
+    oy = round_q22(mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
 }
 
 // Rule step 5 for the four members of an orbit: offsets (ox, oy), (-oy, ox),
@@ -165,9 +165,9 @@ __device__ __forceinline__ void gather_orbit(const Keypoint &k, GlobalByte *img,
     if (k.interior) {
         // Every sample is inside the image, so |offset| * pitch < 2^31 and the
         // 24-bit multiply-adds are exact.
-        const int base = k.cy * k.pitch + k.cx;
-        const int t = mad_i24(oy, k.pitch, ox);
-        const int w = mad_i24(ox, k.pitch, -oy);
+        const int base = k.centre;
+        const int t = mad_i24_s(k.pitch, oy, ox);
+        const int w = mad_i24_s(k.pitch, ox, -oy);
         a0 = (uint32_t)(base + t);
         a1 = (uint32_t)(base + w);
         a2 = (uint32_t)(base - t);
@@ -191,7 +191,7 @@ __device__ __forceinline__ uint32_t gather_single(const Keypoint &k, GlobalByte 
 {
     int ox, oy;
     offsets(k, uv, ox, oy);
-    if (k.interior) return img[(uint32_t)(k.cy * k.pitch + k.cx + mad_i24(oy, k.pitch, ox))];
+    if (k.interior) return img[(uint32_t)(k.centre + mad_i24_s(k.pitch, oy, ox))];
     const int x = clamp_med3(k.cx + ox, 0, k.width - 1);
     const int y = clamp_med3(k.cy + oy, 0, k.height - 1);
     return img[(uint32_t)mad_i24(y, k.pitch, x)];
@@ -383,6 +383,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     if (n_dev) n = min(n, *n_dev);
     int64_t p = blockIdx.x;
     if (p >= n) return;
+    // This lane's output bits 256 w + 64 k + lane come from slots
+    // (slots >> 8 k) & 0xff of its wavefront (constant over keypoints).
+    const uint32_t slots = unperm[64 * wave + lane];
     const int64_t stride = gridDim.x;
     const Slots sl = thread_slots(tid);
     uint32_t g[kSamples];
@@ -427,7 +430,6 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         // Back to triplet order through this wavefront's 8 ballot words in
         // LDS (written and read by the same wavefront, so in order).
         if (lane < 2 * kRoundsPerWave) ballots[lane] = slot_word;
-        const uint32_t slots = unperm[64 * wave + lane];
         uint32_t out_word = 0;
 #pragma unroll
         for (int k = 0; k < kRoundsPerWave; ++k) {

@@ -47,6 +47,24 @@ __device__ __forceinline__ int mad_i24(int a, int b, int c)
     return r;
 }
 
+// The same with a wavefront-uniform first factor `a` read from a scalar
+// register (no copy into a vector register first).
+__device__ __forceinline__ int mul_i24_s(int a, int b)
+{
+    int r;
+    asm("v_mul_i32_i24 %0, %1, %2" : "=v"(r) : "s"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ int mad_i24_s(int a, int b, int c)
+{
+    int r;
+    asm("v_mad_i32_i24 %0, %1, %2, %3" : "=v"(r) : "s"(a), "v"(b), "v"(c));
+    return r;
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc)
 {
     return __builtin_amdgcn_udot4(a, b, acc, false);
@@ -61,6 +79,7 @@ struct Keypoint {
     int c, s, sq;   // C[b], S[b] (Q14) and the Q8 scale
     const uint8_t *img;
     int height, width, pitch;
+    int centre;     // cy * pitch + cx (meaningful when interior)
 };
 
 // Where keypoints find their image: one image given by value, or a device
@@ -158,16 +177,22 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, co
     if (kTable) {
         // The keypoint's image entry, a uniform (scalar) load; the entry was
         // validated per lane in prepare_batch, and ok is false otherwise.
+        // The fields go to scalar registers: every use below is uniform.
         const ImageEntry e = src.table[__builtin_amdgcn_readlane(kb.id, j)];
-        k.img = e.img;
-        k.height = e.height;
-        k.width = e.width;
-        k.pitch = e.pitch;
+        const uint64_t ip = reinterpret_cast<uintptr_t>(e.img);
+        k.img = reinterpret_cast<const uint8_t *>(
+            (uint64_t)(uint32_t)uniform_int((int)(uint32_t)ip) |
+            ((uint64_t)(uint32_t)uniform_int((int)(uint32_t)(ip >> 32)) << 32));
+        k.height = uniform_int(e.height);
+        k.width = uniform_int(e.width);
+        k.pitch = uniform_int(e.pitch);
     } else {
         k.img = src.img;
         k.height = src.height;
         k.width = src.width;
         k.pitch = src.pitch;
     }
+    // Only an interior keypoint uses it, and then cy * pitch + cx < 2^31.
+    k.centre = k.interior ? k.cy * k.pitch + k.cx : 0;
     return k;
 }
