@@ -21,7 +21,9 @@ def torch_cuda():
     return torch
 
 
-def run_full(torch, triplets, imgs, kps, seed):
+def run_full(torch, triplets, imgs, kps, seed, plan=False):
+    """Batched extraction and matching of the whole workload (eager calls, or
+    one captured plan replayed twice), then sampled checks against the oracle."""
     from paper_1609_03986_amd.binding import Latch, image_table, pair_table
     lat = Latch(triplets)
     try:
@@ -31,11 +33,29 @@ def run_full(torch, triplets, imgs, kps, seed):
         dimgs = [torch.from_numpy(im).cuda() for im in imgs]
         kp_all = np.concatenate(kps).astype(np.float32)
         ids = np.repeat(np.arange(len(imgs), dtype=np.int32), counts)
-        desc = lat.extract_batch(image_table(dimgs), len(imgs), torch.from_numpy(ids).cuda(),
-                                 torch.from_numpy(kp_all).cuda())
         pairs = np.array([(first[i], counts[i], first[i + 1], counts[i + 1], first[i])
                           for i in range(len(imgs) - 1)], np.int64)
-        idx, dist, acc = lat.knn_batch(desc, desc, pair_table(pairs), total)
+        table = image_table(dimgs)
+        ids_d = torch.from_numpy(ids).cuda()
+        kps_d = torch.from_numpy(kp_all).cuda()
+        if plan:
+            desc = torch.full((total, 16), -7, dtype=torch.int32, device="cuda")
+            idx = torch.full((total, 2), -7, dtype=torch.int32, device="cuda")
+            dist = torch.full((total, 2), -7, dtype=torch.int32, device="cuda")
+            acc = torch.full((total,), 9, dtype=torch.uint8, device="cuda")
+            p = lat.plan(table, len(imgs), ids_d, kps_d, desc, pair_table(pairs), idx, dist, acc)
+            p.run()
+            torch.cuda.synchronize()
+            first_run = (desc.clone(), idx.clone(), dist.clone(), acc.clone())
+            desc.fill_(-7)
+            idx.fill_(-7)
+            p.run()                                           # a replay gives the same outputs
+            torch.cuda.synchronize()
+            assert all(torch.equal(a, b) for a, b in zip(first_run, (desc, idx, dist, acc)))
+            p.close()
+        else:
+            desc = lat.extract_batch(table, len(imgs), ids_d, kps_d)
+            idx, dist, acc = lat.knn_batch(desc, desc, pair_table(pairs), total)
         torch.cuda.synchronize()
         assert lat.check_errors(clear=True) == 0
         D = desc.cpu().numpy().view(np.uint32)
@@ -70,3 +90,13 @@ def test_uneven_batch_full_size(torch_cuda, triplets):
     imgs, kps = synth.uneven_workload()
     assert len(imgs) == 256
     run_full(torch_cuda, triplets, imgs, kps, 2)
+
+
+def test_sfm_batch_full_size_captured_plan(torch_cuda, triplets):
+    imgs, kps = synth.sfm_workload()
+    run_full(torch_cuda, triplets, imgs, kps, 3, plan=True)
+
+
+def test_uneven_batch_full_size_captured_plan(torch_cuda, triplets):
+    imgs, kps = synth.uneven_workload()
+    run_full(torch_cuda, triplets, imgs, kps, 4, plan=True)
