@@ -218,7 +218,8 @@ class Batch:
         self.acc = torch.zeros(self.total, dtype=torch.uint8, device="cuda")
         self.plan = lat.plan(self.table, self.n_img, self.ids, self.kp_all, self.desc, self.pairs,
                              self.idx, self.dist, self.acc, path=path)
-        lat.reserve(lat.knn_batch_workspace_size(self.n_img - 1, self.total))
+        lat.reserve(max(lat.knn_batch_workspace_size(self.n_img - 1, self.total),
+                        lat.extract_batch_workspace_size(self.n_img, self.total)))
 
     def run_plan(self):
         self.plan.run()
@@ -444,7 +445,8 @@ def main():
     _, step_ms = timer.loop(sfm.run_plan, args.steps, 0, per_step=True)
     # Kernel durations: the plan's launches as eager calls, with the library's events.
     kernels = kernel_times(lat, torch, sfm.run_eager, args.steps,
-                           ("extract", "knn_batch_fp4", "knn_batch_mfma", "knn_batch_popcount"))
+                           ("extract_order", "extract", "knn_batch_fp4", "knn_batch_mfma",
+                            "knn_batch_popcount"))
     eager_wall, _ = timer.loop(sfm.run_eager, args.steps, 1)
     roof = roofline_of(kernels, total, n_pairs, "sfm")
     log("timed %d steps: %.3f ms per step" % (args.steps, ms_per_step))

@@ -27,8 +27,9 @@
  *       latch_destroy, latch_plan_destroy: the whole device.
  *   - A handle owns device copies of the rotation table and triplet table,
  *     a sticky error word and a workspace that only latch_reserve sizes.
- *     hamming_knn (with more than one train split), hamming_knn_batch and
- *     latch_detect need workspace; the *_workspace_size calls give the bytes
+ *     hamming_knn (with more than one train split), hamming_knn_batch,
+ *     latch_detect and large batched extractions need workspace; the
+ *     *_workspace_size calls give the bytes
  *     for given sizes, and a call whose need exceeds what the handle holds
  *     returns LATCH_EWORKSPACE and enqueues nothing.  A handle is not
  *     thread-safe, and work enqueued through one handle on different streams
@@ -162,11 +163,19 @@ void latch_destroy(latch_handle h);
  *     the work-item list of the persistent matcher.
  *   latch_detect_workspace_size: survivor masks, counts and row offsets of
  *     an image of height x width.
+ *   latch_extract_batch_workspace_size: a latch_create handle orders a batch
+ *     of at least 2^18 keypoints (max_kps) over at most 65536 images by
+ *     (image, band of rows) before extracting it, so that each XCD's L2
+ *     holds the image rows its workgroups read; 12 bytes per keypoint plus
+ *     about 256 bytes per image for the counting sort.  0 for smaller
+ *     batches and for geometry handles (extracted in the given order).
  * LATCH_EINVAL for a NULL pointer or sizes outside the limits of the call.
  */
 int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path, size_t *bytes);
 int hamming_knn_batch_workspace_size(latch_handle h, int n_pairs, int64_t out_rows, size_t *bytes);
 int latch_detect_workspace_size(latch_handle h, int height, int width, size_t *bytes);
+int latch_extract_batch_workspace_size(latch_handle h, int n_images, int64_t max_kps,
+                                       size_t *bytes);
 
 /*
  * Make the handle's workspace at least `bytes` (a set-up call, made before
@@ -214,6 +223,9 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
  * violates the limits above or has a NULL pointer, gets an all-zero
  * descriptor and sets LATCH_FLAG_BAD_IMAGE.  Host-checked: max_kps in
  * [0, 2^31), n_images >= 1 when max_kps > 0, non-NULL buffers (LATCH_EINVAL).
+ * Large batches use the handle's workspace for their spatial order
+ * (latch_extract_batch_workspace_size; LATCH_EWORKSPACE if it holds less);
+ * the descriptors do not depend on it.
  */
 int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_images,
                         const int32_t *image_id_dev, const latch_keypoint *kps_dev,

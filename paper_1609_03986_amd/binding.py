@@ -33,7 +33,8 @@ STATUS_NAMES = {0: "LATCH_OK", -1: "LATCH_EINVAL", -2: "LATCH_ENOMEM", -3: "LATC
 
 # Every symbol include/latch.h declares.
 EXPORTS = ("latch_create", "latch_create_geometry", "latch_destroy", "hamming_knn_workspace_size",
-           "hamming_knn_batch_workspace_size", "latch_detect_workspace_size", "latch_reserve",
+           "hamming_knn_batch_workspace_size", "latch_detect_workspace_size",
+           "latch_extract_batch_workspace_size", "latch_reserve",
            "latch_extract", "latch_extract_batch",
            "latch_extract_dense", "hamming_knn_window", "latch_detect",
            "hamming_knn", "hamming_knn_noalloc",
@@ -82,6 +83,8 @@ def load_library():
     lib.hamming_knn_batch_workspace_size.restype = I
     lib.latch_detect_workspace_size.argtypes = [P, I, I, SZ]
     lib.latch_detect_workspace_size.restype = I
+    lib.latch_extract_batch_workspace_size.argtypes = [P, I, I64, SZ]
+    lib.latch_extract_batch_workspace_size.restype = I
     lib.latch_reserve.argtypes = [P, ctypes.c_size_t, SZ]
     lib.latch_reserve.restype = I
     lib.latch_extract.argtypes = [P, P, I, I, I, P, I64, P, P]
@@ -162,6 +165,12 @@ def hamming_knn_batch_workspace_size(h, n_pairs, out_rows):
 
 def latch_detect_workspace_size(h, height, width):
     return _size_out(h, load_library().latch_detect_workspace_size, int(height), int(width))
+
+
+def latch_extract_batch_workspace_size(h, n_images, max_kps):
+    """Workspace bytes of a batched extraction's spatial order (0 if none)."""
+    return _size_out(h, load_library().latch_extract_batch_workspace_size, int(n_images),
+                     int(max_kps))
 
 
 def latch_reserve(h, nbytes=0):
@@ -342,11 +351,11 @@ def latch_extract_batch(h, table, n_images, image_id, kps, desc=None, n_kps=None
     if desc is None:
         desc = torch.empty((n, 16), dtype=torch.int32, device=kps.device)
     nptr = _dev(n_kps, torch.int64, "n_kps") if n_kps is not None else None
-    rc = load_library().latch_extract_batch(h, _dev(table, torch.uint8, "table"), int(n_images),
-                                            _dev(image_id, torch.int32, "image_id"),
-                                            _dev(kps, torch.float32, "kps"), n, nptr,
-                                            _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
-    _check(h, rc)
+    args = (h, _dev(table, torch.uint8, "table"), int(n_images),
+            _dev(image_id, torch.int32, "image_id"), _dev(kps, torch.float32, "kps"), n, nptr,
+            _dev(desc, torch.int32, "desc"), _stream_ptr(stream))
+    _with_workspace(h, lambda: load_library().latch_extract_batch(*args),
+                    lambda: latch_extract_batch_workspace_size(h, n_images, n))
     return desc
 
 
@@ -581,6 +590,9 @@ class Latch:
 
     def detect_workspace_size(self, height, width):
         return latch_detect_workspace_size(self.h, height, width)
+
+    def extract_batch_workspace_size(self, n_images, max_kps):
+        return latch_extract_batch_workspace_size(self.h, n_images, max_kps)
 
     def knn(self, query, train, k=2, ratio=0.8, path="auto", **kw):
         return hamming_knn(self.h, query, train, k, ratio, path, **kw)

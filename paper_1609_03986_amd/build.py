@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblatch.so")
-SOURCES = ["runtime.hip", "extract.hip", "extract_weighted.hip", "knn.hip", "detect.hip", "dense.hip"]
+SOURCES = ["runtime.hip", "extract.hip", "extract_weighted.hip", "order.hip", "knn.hip", "detect.hip",
+           "dense.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -379,14 +379,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     uint32_t *ballots = reinterpret_cast<uint32_t *>(lds + kBallotBase) + 8 * wave;
 
     // Keypoint count: a host value, or (batches) a device value capped by it.
-    int64_t n = n_host;
-    if (n_dev) n = min(n, *n_dev);
-    int64_t p = blockIdx.x;
+    int64_t n_all = n_host;
+    if (n_dev) n_all = min(n_all, *n_dev);
+    const KeypointRange range = xcd_range(n_all);
+    const int64_t n = range.end;
+    int64_t p = range.first;
     if (p >= n) return;
     // This lane's output bits 256 w + 64 k + lane come from slots
     // (slots >> 8 k) & 0xff of its wavefront (constant over keypoints).
     const uint32_t slots = unperm[64 * wave + lane];
-    const int64_t stride = gridDim.x;
+    const int64_t stride = range.stride;
     const Slots sl = thread_slots(tid);
     uint32_t g[kSamples];
     KeypointBatch batch = prepare_batch<kTable, kHalf>(kps, n, p, stride, lane, rot, src);
@@ -396,8 +398,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
 
     for (int i = 0; p < n; ++i, p += stride) {
         const bool compute = cur.ok;
+        // Descriptor row of this position's keypoint (the position itself
+        // unless a batch order permutes the keypoints).
+        const int64_t q = kTable && src.order ? (int64_t)cur.key : p;
         if (!compute) {
-            if (tid < kWords) uniform_words(desc + p * kWords)[(uint32_t)tid] = 0u;
+            if (tid < kWords) uniform_words(desc + q * kWords)[(uint32_t)tid] = 0u;
             if (tid == 0) atomicOr(flags, bad_image ? kFlagBadImage : kFlagBadKeypoint);
         } else {
             // The raw window was last read by the previous descriptor's copy
@@ -439,7 +444,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
             if (lane == 2 * k + 1) out_word = (uint32_t)(bits >> 32);
         }
         if (lane < 2 * kRoundsPerWave)
-            uniform_words(desc + (p * kWords + 2 * kRoundsPerWave * wave))[(uint32_t)lane] = out_word;
+            uniform_words(desc + (q * kWords + 2 * kRoundsPerWave * wave))[(uint32_t)lane] = out_word;
     }
 }
 
@@ -451,7 +456,7 @@ hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream)
     int64_t blocks = a.n;
     const int64_t resident = (int64_t)a.num_cus * (kLdsPerCu / kWinLdsBytes);
     if (blocks > resident) blocks = resident;
-    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
+    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images, a.order};
     if (a.table)
         hipLaunchKernelGGL(extract_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
                            src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.desc, a.flags);

@@ -179,11 +179,13 @@ __global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
     const uint32_t un = unperm[64 * wave + lane];
     uint32_t *bw = ballot_words + 4 * wave;
 
-    int64_t n = n_host;
-    if (n_dev) n = min(n, *n_dev);
-    int64_t p = blockIdx.x;
+    int64_t n_all = n_host;
+    if (n_dev) n_all = min(n_all, *n_dev);
+    const KeypointRange range = xcd_range(n_all);
+    const int64_t n = range.end;
+    int64_t p = range.first;
     if (p >= n) return;
-    const int64_t stride = gridDim.x;
+    const int64_t stride = range.stride;
     uint32_t g[G::kSamples];
     KeypointBatch batch = prepare_batch<kTable, G::kHalfW>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
@@ -233,7 +235,7 @@ hipError_t launch_weighted_w(const ExtractArgs &a, hipStream_t stream)
     int64_t blocks = a.n;
     const int64_t resident = (int64_t)a.num_cus * (kLdsPerCu / WGeom<kW>::kLds);
     if (blocks > resident) blocks = resident;
-    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images};
+    ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images, nullptr};
     if (a.table)
         hipLaunchKernelGGL((extract_weighted_kernel<true, kW>), dim3((unsigned)blocks), dim3(kWThreads),
                            0, stream, src, a.kps, a.n, a.n_dev, a.rot, a.wtrip_off, a.wunperm, a.weights,

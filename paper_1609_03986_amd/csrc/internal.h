@@ -84,9 +84,27 @@ struct ExtractArgs {
     const uint2 *wtrip_off = nullptr;   // [512] by slot: LDS byte offsets of the patches
     const uint32_t *wunperm = nullptr;  // [256] per (wavefront, lane): slots of its two output bits
     WeightRows weights = {};
+    // Batches: keypoint index at each position of a spatial order (default
+    // kernel only), or nullptr to take the keypoints as given.
+    const int32_t *order = nullptr;
 };
 
 hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream);
+
+// Spatial order of a batch's keypoints: (image, band of rows) buckets, a
+// counting sort in the handle's or plan's workspace.  Batches of at least
+// kOrderMinKeypoints keypoints (max_kps) are ordered before extraction.
+constexpr int kOrderBandRows = 32;
+constexpr int kOrderMaxBands = 64;
+constexpr int64_t kOrderMinKeypoints = 1 << 18;
+
+struct OrderLayout {
+    int64_t max_buckets;                          // kOrderMaxBands * n_images + 1
+    size_t band_base, counts, bucket, rank, order, total;   // byte offsets, total bytes
+};
+OrderLayout order_layout(int n_images, int64_t max_kps);
+// Enqueues the order's five kernels; the order lands at ws + order_layout().order.
+hipError_t launch_order(const ExtractArgs &a, uint8_t *ws, hipStream_t stream);
 hipError_t launch_extract_weighted(const ExtractArgs &a, hipStream_t stream);
 // LDS byte offset of the top-left pixel (top, left) of a patch in the
 // weighted kernel's window of side `window` (48 or 64).

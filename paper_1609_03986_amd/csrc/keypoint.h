@@ -70,6 +70,35 @@ __device__ __forceinline__ uint32_t dot4(uint32_t a, uint32_t b, uint32_t acc)
     return __builtin_amdgcn_udot4(a, b, acc, false);
 }
 
+// The keypoints one workgroup of a grid-stride extraction takes.  The chip's
+// 8 XCDs (workgroups go to them round-robin by index) take contiguous eighths
+// of [0, n), so that one XCD's L2 holds the images (or, for keypoints in
+// raster order, the image rows) its own workgroups read, rather than every
+// XCD fetching every image; within its eighth an XCD's workgroups stride
+// over the keypoints.  Keypoint p of the range is first + m * stride.
+struct KeypointRange {
+    int64_t first, end, stride;
+};
+
+__device__ __forceinline__ KeypointRange xcd_range(int64_t n)
+{
+    constexpr int kXcds = 8;
+    const int g = gridDim.x, b = blockIdx.x;
+    KeypointRange r;
+    if (g < kXcds) {
+        r.first = b;
+        r.end = n;
+        r.stride = g;
+        return r;
+    }
+    const int xcd = b % kXcds;
+    const int64_t per = (n + kXcds - 1) / kXcds;
+    r.first = (int64_t)xcd * per + b / kXcds;
+    r.end = min(n, (int64_t)(xcd + 1) * per);
+    r.stride = (g - xcd + kXcds - 1) / kXcds;     // workgroups on this XCD
+    return r;
+}
+
 // Rule steps 1-3 for one keypoint (uniform across the workgroup), with the
 // image it samples.
 struct Keypoint {
@@ -80,6 +109,7 @@ struct Keypoint {
     const uint8_t *img;
     int height, width, pitch;
     int centre;     // cy * pitch + cx (meaningful when interior)
+    int key;        // the keypoint's index in the keypoint and descriptor arrays
 };
 
 // Where keypoints find their image: one image given by value, or a device
@@ -90,6 +120,7 @@ struct ImageSource {
     const ImageEntry *table;     // batch: table[image_id[k]]
     const int32_t *image_id;
     int n_images;
+    const int32_t *order;        // batch: keypoint index at each position, or nullptr (identity)
 };
 
 // Rule steps 1-3 for 64 keypoints at once: lane j takes keypoint
@@ -101,6 +132,7 @@ struct KeypointBatch {
     int cs;          // C[b] & 0xffff | S[b] << 16
     int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18
     int id;          // image table: the keypoint's image (0 when out of range)
+    int key;         // keypoint index (the position itself without an order)
 };
 
 // kHalfSide: the largest |u|, |v| of a window position (half the window side).
@@ -111,8 +143,9 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
                                                        const ImageSource &src)
 {
     KeypointBatch kb;
-    const int64_t idx = first + stride * lane;
+    int64_t idx = first + stride * lane;
     const bool real = idx < n;
+    if (kTable && src.order && real) idx = src.order[idx];
     const uint8_t *img = src.img;
     int height = src.height, width = src.width, pitch = src.pitch;
     bool image_ok = true;
@@ -156,6 +189,7 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
     kb.cs = (cs.x & 0xffff) | (cs.y << 16);
     kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18);
     kb.id = image_id;
+    kb.key = (int)idx;
     return kb;
 }
 
@@ -164,6 +198,7 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, co
                                               bool *bad_image)
 {
     Keypoint k;
+    k.key = __builtin_amdgcn_readlane(kb.key, j);
     k.cx = __builtin_amdgcn_readlane(kb.cx, j);
     k.cy = __builtin_amdgcn_readlane(kb.cy, j);
     const int cs = __builtin_amdgcn_readlane(kb.cs, j);

@@ -455,6 +455,33 @@ hipError_t run_extract(const ExtractArgs &a, hipStream_t stream)
     return a.window ? launch_extract_weighted(a, stream) : launch_extract(a, stream);
 }
 
+// Workspace of a batched extraction's spatial order (0: extracted as given).
+constexpr int kOrderMaxImages = 1 << 16;
+
+size_t extract_batch_workspace(latch_handle h, int n_images, int64_t max_kps)
+{
+    if (h->window || max_kps < kOrderMinKeypoints || n_images < 1 || n_images > kOrderMaxImages)
+        return 0;
+    return order_layout(n_images, max_kps).total;
+}
+
+// A batched extraction: the order's kernels (when the batch has one, in
+// workspace `ws`), then the extraction kernel.  A plan's capture records no
+// timing events (timed = false).
+hipError_t run_extract_batch(latch_handle h, ExtractArgs a, uint8_t *ws, hipStream_t stream,
+                             bool timed)
+{
+    auto launch = [&](const char *name, auto &&f) {
+        return timed ? timed_launch(h, name, stream, f) : f();
+    };
+    if (extract_batch_workspace(h, a.n_images, a.n) > 0) {
+        const hipError_t e = launch("extract_order", [&] { return launch_order(a, ws, stream); });
+        if (e != hipSuccess) return e;
+        a.order = reinterpret_cast<const int32_t *>(ws + order_layout(a.n_images, a.n).order);
+    }
+    return launch("extract", [&] { return run_extract(a, stream); });
+}
+
 // Scratch of hamming_knn_noalloc: a static device array, one copy per GPU
 // the library runs on, held until the process ends.  Host code never names
 // it directly (on the host `scratch` is only a stand-in symbol): it uses the
@@ -792,9 +819,12 @@ int latch_extract_batch(latch_handle h, const latch_image *images_dev, int n_ima
     if (max_kps == 0) return LATCH_OK;
     if (!images_dev || !image_id_dev || !kps_dev || !desc_dev || n_images == 0)
         return fail(h, LATCH_EINVAL, "null buffer or empty image table");
+    const int rc = check_workspace(h, extract_batch_workspace(h, n_images, max_kps),
+                                   "latch_extract_batch");
+    if (rc != LATCH_OK) return rc;
     const ExtractArgs a = batch_extract_args(h, images_dev, n_images, image_id_dev, kps_dev,
                                              max_kps, n_kps_dev, desc_dev);
-    hipError_t e = timed_launch(h, "extract", stream, [&] { return run_extract(a, stream); });
+    const hipError_t e = run_extract_batch(h, a, h->ws, stream, true);
     return e == hipSuccess ? LATCH_OK : hip_fail(h, e, "batched extract launch");
 }
 
@@ -947,6 +977,17 @@ int latch_detect_workspace_size(latch_handle h, int height, int width, size_t *b
     return LATCH_OK;
 }
 
+int latch_extract_batch_workspace_size(latch_handle h, int n_images, int64_t max_kps,
+                                       size_t *bytes)
+{
+    if (!h || !bytes) return LATCH_EINVAL;
+    if (n_images < 0 || max_kps < 0 || max_kps > LATCH_MAX_ROWS)
+        return fail(h, LATCH_EINVAL, "n_images = %d, max_kps = %lld out of range", n_images,
+                    (long long)max_kps);
+    *bytes = extract_batch_workspace(h, n_images, max_kps);
+    return LATCH_OK;
+}
+
 int latch_reserve(latch_handle h, size_t bytes, size_t *held_out)
 {
     if (!h) return LATCH_EINVAL;
@@ -1086,7 +1127,10 @@ int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
 
     latch_plan_ctx *p = new latch_plan_ctx();
     p->h = h;
-    hipError_t e = hipMalloc((void **)&p->ws, batch_workspace_bytes(d->n_pairs, d->out_rows));
+    // Plan workspace: the matcher's state, then the extraction's order.
+    const size_t knn_bytes = align_up(batch_workspace_bytes(d->n_pairs, d->out_rows), 256);
+    const size_t order_bytes = extract_batch_workspace(h, d->n_images, d->max_kps);
+    hipError_t e = hipMalloc((void **)&p->ws, knn_bytes + order_bytes);
     if (e != hipSuccess) {
         delete p;
         return hip_fail(h, e, "hipMalloc(plan workspace)");
@@ -1100,7 +1144,7 @@ int latch_plan_create(latch_handle h, const latch_plan_desc *d, latch_plan *out)
     hipStream_t s = nullptr;
     e = hipStreamCreateWithFlags(&s, hipStreamNonBlocking);
     if (e == hipSuccess) e = hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess && d->max_kps > 0) e = run_extract(ea, s);
+    if (e == hipSuccess && d->max_kps > 0) e = run_extract_batch(h, ea, p->ws + knn_bytes, s, false);
     if (e == hipSuccess && d->n_pairs > 0) e = launch_knn_batch(ba, s);
     hipGraph_t graph = nullptr;
     if (s) {

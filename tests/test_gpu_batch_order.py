@@ -1,0 +1,154 @@
+"""GPU parity of batched extraction with the spatial order (batches of at
+least 2^18 keypoints are counting-sorted by image and band of rows before
+extraction): every descriptor lands in its own keypoint's row, bit-exact
+against the single-image call and, on a sample, the oracle; malformed
+keypoints and image entries still give zero rows and their flags; a device
+count limits the order as it limits the extraction; the order's workspace is
+reserved like any other."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1609_03986_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ORDER_MIN = 1 << 18
+SENTINEL = -0x55555556
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def make_batch(seed, sizes, n):
+    """n keypoints over images of the given sizes, interleaved at random, with
+    some windows clamping at the borders and some malformed entries."""
+    g = np.random.default_rng(seed)
+    imgs = [synth.smoothed_noise(g, h, w) for h, w in sizes]
+    ids = g.integers(0, len(sizes), n).astype(np.int32)
+    kps = np.zeros((n, 4), np.float32)
+    for i, (h, w) in enumerate(sizes):
+        sel = np.nonzero(ids == i)[0]
+        kps[sel] = synth.random_keypoints(g, len(sel), h, w, margin=-8)
+    bad_id = g.choice(n, 40, replace=False)
+    ids[bad_id[:20]] = -1
+    ids[bad_id[20:]] = len(sizes) + 3
+    bad_y = g.choice(np.setdiff1d(np.arange(n), bad_id), 20, replace=False)
+    kps[bad_y, 1] = np.nan
+    return imgs, kps, ids
+
+
+def single_calls(torch, lat, dev_imgs, kps, ids):
+    """Each image's keypoints through the single-image call (never ordered)."""
+    want = np.zeros((len(kps), 16), np.uint32)
+    for i, im in enumerate(dev_imgs):
+        sel = np.nonzero(ids == i)[0]
+        if len(sel):
+            d = lat.extract(im, torch.from_numpy(kps[sel]).cuda())
+            torch.cuda.synchronize()
+            want[sel] = d.cpu().numpy().view(np.uint32)
+    return want
+
+
+def test_order_workspace_size(torch_cuda, triplets):
+    from paper_1609_03986_amd.binding import Latch
+    lat = Latch(triplets)
+    try:
+        assert lat.extract_batch_workspace_size(5, ORDER_MIN - 1) == 0
+        assert lat.extract_batch_workspace_size(5, 0) == 0
+        need = lat.extract_batch_workspace_size(5, ORDER_MIN)
+        assert 12 * ORDER_MIN <= need <= 12 * ORDER_MIN + 5 * 4096
+        assert lat.extract_batch_workspace_size(1 << 16, ORDER_MIN) > need
+        assert lat.extract_batch_workspace_size((1 << 16) + 1, ORDER_MIN) == 0   # too many images
+    finally:
+        lat.close()
+
+
+def test_ordered_batch_equals_single_calls(torch_cuda, triplets):
+    torch = torch_cuda
+    from paper_1609_03986_amd import binding
+    from paper_1609_03986_amd.binding import FLAG_BAD_IMAGE, FLAG_BAD_KEYPOINT, Latch, image_table
+    sizes = [(480, 640), (2000, 300), (37, 2500), (3000, 40), (1, 1), (1100, 1900), (64, 64)]
+    n = ORDER_MIN + 37_000                      # ragged: not a multiple of any tile
+    imgs, kps, ids = make_batch(11, sizes, n)
+    dev_imgs = [torch.from_numpy(im).cuda() for im in imgs]
+    table = image_table(dev_imgs)
+    table[24 * 6:24 * 6 + 8] = 0                # image 6: a NULL pointer entry
+    k = torch.from_numpy(kps).cuda()
+    idt = torch.from_numpy(ids).cuda()
+    lat = Latch(triplets)
+    try:
+        # A fresh handle holds no workspace: the call fails and writes nothing.
+        out = torch.full((n, 16), SENTINEL, dtype=torch.int32, device="cuda")
+        lib = binding.load_library()
+        ptr = lambda t: ctypes.c_void_p(t.data_ptr())
+        rc = lib.latch_extract_batch(lat.h, ptr(table), len(sizes), ptr(idt), ptr(k), n, None,
+                                     ptr(out), None)
+        assert rc == binding.LATCH_EWORKSPACE
+        assert b"latch_reserve" in lib.latch_last_error(lat.h)
+        torch.cuda.synchronize()
+        assert (out == SENTINEL).all()
+
+        lat.reserve(lat.extract_batch_workspace_size(len(sizes), n))
+        lat.timing(True)
+        lat.extract_batch(table, len(sizes), idt, k, desc=out)
+        torch.cuda.synchronize()
+        assert lat.timing_read("extract_order")[0] == 1          # the order ran
+        lat.timing(False)
+        got = out.cpu().numpy().view(np.uint32)
+        flags = lat.check_errors(clear=True)
+        assert flags == FLAG_BAD_IMAGE | FLAG_BAD_KEYPOINT
+
+        bad_image = (ids < 0) | (ids >= len(sizes)) | (ids == 6)
+        assert not got[bad_image].any()
+        want = single_calls(torch, lat, dev_imgs[:6], kps, np.where(bad_image, -1, ids))
+        lat.check_errors(clear=True)
+        assert np.array_equal(got, want)
+
+        # The oracle on a sample of the well-formed rows.
+        good = np.nonzero(~bad_image & np.isfinite(kps[:, 1]))[0][::97]
+        for i in range(6):
+            sel = good[ids[good] == i]
+            if len(sel):
+                d, f = oracle.extract(imgs[i], kps[sel], triplets)
+                assert f == 0
+                assert np.array_equal(got[sel], d)
+    finally:
+        lat.close()
+
+
+def test_device_count_limits_the_order(torch_cuda, triplets):
+    torch = torch_cuda
+    from paper_1609_03986_amd.binding import Latch, image_table
+    sizes = [(900, 1200), (300, 2800), (2200, 500)]
+    n = ORDER_MIN + 5000
+    imgs, kps, ids = make_batch(12, sizes, n)
+    ids = np.clip(ids, 0, len(sizes) - 1)
+    kps[:, 1] = np.nan_to_num(kps[:, 1], nan=5.0)
+    dev_imgs = [torch.from_numpy(im).cuda() for im in imgs]
+    table = image_table(dev_imgs)
+    k = torch.from_numpy(kps).cuda()
+    idt = torch.from_numpy(ids).cuda()
+    lat = Latch(triplets)
+    try:
+        full = lat.extract_batch(table, len(sizes), idt, k).cpu().numpy().view(np.uint32)
+        m = n - 12_345
+        out = torch.full((n, 16), SENTINEL, dtype=torch.int32, device="cuda")
+        lat.extract_batch(table, len(sizes), idt, k, desc=out,
+                          n_kps=torch.tensor([m], dtype=torch.int64, device="cuda"))
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32)
+        assert np.array_equal(got[:m], full[:m])
+        assert np.all(got[m:] == 0xAAAAAAAA)     # untouched past the device count
+        assert lat.check_errors(clear=True) == 0
+        want = single_calls(torch, lat, dev_imgs, kps, ids)
+        assert np.array_equal(full, want)
+    finally:
+        lat.close()
