@@ -16,8 +16,8 @@
 //   v_bcnt) per pair.
 //
 // Top-2 selection packs (distance, split-local index) into one 32-bit key so
-// that one min/max and one med3 keep the two best per lane; ties resolve to
-// the lowest index because the index is part of the key.  Each (query,
+// that a max3, a med3 and a max fold two keys into the two best per lane;
+// ties resolve to the lowest index because the index is part of the key.  Each (query,
 // train split) writes its best two as 64-bit (distance << 32 | index) values;
 // a merge kernel reduces over splits and applies the ratio test.
 #include "internal.h"
@@ -34,6 +34,18 @@ constexpr uint32_t kLocalMask = (1u << kLocalBits) - 1;
 __device__ __forceinline__ uint32_t umed3(uint32_t a, uint32_t b, uint32_t c)
 {
     return max(min(a, b), min(max(a, b), c));
+}
+
+// Two keys x, y into a running top two (k1 >= k2, as a multiset): the new
+// largest is max(k1, x, y); the new second is max(k2, med3(k1, x, y)), since
+// if k1 stays largest the second is max(k2, x, y) = max(k2, med3), and if x
+// (or y) is largest the second is max(k1, y) (or max(k1, x)), which is the
+// median of k1, x, y and is >= k2.  Three operations per two keys, against
+// two per key inserted one at a time.
+__device__ __forceinline__ void insert_pair_u32(uint32_t &k1, uint32_t &k2, uint32_t x, uint32_t y)
+{
+    k2 = max(k2, umed3(k1, x, y));
+    k1 = max(max(k1, x), y);
 }
 
 
@@ -275,13 +287,11 @@ __device__ __forceinline__ void mfma_item(const uint32_t *__restrict__ query, in
             }
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < 16; r += 2) {
 #pragma unroll
-            for (int qb = 0; qb < kQueryBlocks; ++qb) {
-                const uint32_t key = ((uint32_t)acc[qb][r] << kLocalBits) + cb[r];
-                k2[qb] = umed3(k1[qb], k2[qb], key);
-                k1[qb] = max(k1[qb], key);
-            }
+            for (int qb = 0; qb < kQueryBlocks; ++qb)
+                insert_pair_u32(k1[qb], k2[qb], ((uint32_t)acc[qb][r] << kLocalBits) + cb[r],
+                                ((uint32_t)acc[qb][r + 1] << kLocalBits) + cb[r + 1]);
         }
     };
 
@@ -337,11 +347,12 @@ __device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c
 // matrix instruction v_mfma_scale_f32_32x32x64_f8f6f4 (K = 64 per
 // instruction, twice the int8 rate on gfx950).
 //
-// Operands.  FP4 (e2m1) holds 0 (0x0), +1 (0x2) and -1 (0xa) exactly.
-// Train bits enter as 0 / +1 with block scale 2^0, query bits as
-// +1 / -1 (set / clear) with block scale 2^14, so each product is 0 or
-// +-2^14 and the f32 sum over K = 512 is 2^14 s with s = |a| - Hamming(a, b)
-// as in the int8 path, exact (|2^14 s| <= 2^23).
+// Operands.  FP4 (e2m1) holds 0 (0x0), +-0.5 (0x1 / 0x9), +-1 (0x2 / 0xa)
+// and +-2 (0x4 / 0xc) exactly.  A train bit enters as 0 or c (c = 0.5, 1 or
+// 2 by its place in the fragment, below) with block scale 2^0, and the query
+// bit it meets as +1 / c or -1 / c (set / clear) with block scale 2^14, so
+// each product is 0 or +-2^14 and the f32 sum over K = 512 is 2^14 s with
+// s = |a| - Hamming(a, b) as in the int8 path, exact (|2^14 s| <= 2^23).
 //
 // Keys.  For tile row m the accumulator starts at c_m = 2^14 - 1 - m, so it
 // ends at 2^14 s + c_m; the running top-2 of a lane is kept in the frame of
@@ -350,19 +361,25 @@ __device__ __forceinline__ void top2_pair(uint64_t &a1, uint64_t &a2, uint64_t c
 // after T tiles (T < 512): integers below 2^24 in magnitude, exact in f32.
 // For a fixed query the largest key is the smallest (distance, index).  Rows
 // past nt (last tile only) start at -2^25 instead, below every real key,
-// which also marks "no neighbour".  Top-2 selection is one v_max_f32 and
-// one v_med3_f32 per pair.
+// which also marks "no neighbour".  Top-2 selection takes the keys two at a
+// time: v_med3_f32, v_max3_f32 and v_max_f32 per two pairs.
 //
 // Fragment order.  Step s (0..7), lane l: the 32 elements of row l % 32 at
-// K = 64 s + 32 (l / 32) + e are packed word 2 s + l / 32 of that row, bit e
-// -> nibble e (16 bytes).  Queries use the same map.  Bytes expand to FP4
-// through a 256-entry table in LDS (byte -> 8 nibbles).
+// K = 64 s + 32 (l / 32) + 0..31 are the bits of packed word 2 s + l / 32 of
+// that row, bit 4 i + j in nibble i of dword j (16 bytes); queries use the
+// same map, so the K sum covers every bit once.  In this order a train word
+// becomes FP4 with four AND masks and one shift, no table: dword j keeps its
+// bits where they are, as nibble bit 0, 1, 2 (values 0.5, 1, 2) for
+// j = 0, 1, 2, and bit 3 (the sign) is moved down to bit 2 for j = 3, so
+// c = 0.5, 1, 2, 2 by dword.
 //
 // Tile shape.  A wavefront holds QB blocks of 32 queries (QB = 2 or 3, from
 // the tuning table), so each train fragment read from LDS feeds QB MFMAs and
-// each staged tile serves 128 QB queries of the workgroup.  Measured on the
-// SfM batch (63 pairs of 20k x 20k): 5.0 ms per batched launch at QB = 2,
-// 4.76 ms at QB = 3 (whose 256 VGPRs hold 96 of query fragments).
+// each staged tile serves 128 QB queries of the workgroup.  Measured on 63
+// pairs of 20k x 20k random descriptors: 4.98 ms per batched launch with
+// the table-based expansion and one-key insertion, 4.70 ms with the masks
+// and two-key insertion (QB = 3, whose 256 VGPRs hold 96 of query
+// fragments; QB = 2 is about 5% slower).
 // ---------------------------------------------------------------------------
 typedef float v16f __attribute__((ext_vector_type(16)));
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -373,30 +390,42 @@ constexpr int kFp4ScaleTrain = 127;                   // E8M0 2^0
 constexpr int kFp4ScaleQuery = 127 + 14;              // E8M0 2^14
 constexpr float kFp4None = -33554432.0f;              // -2^25
 
-// Byte -> 8 FP4 nibbles (bit e -> nibble e): `one` for a set bit, `zero` for a clear one.
-__device__ __forceinline__ uint32_t fp4_byte(uint32_t byte, uint32_t one, uint32_t zero)
+// Train word -> its four FP4 dwords (0 or c per bit, c = 0.5, 1, 2, 2).
+__device__ __forceinline__ uint4 fp4_train(uint32_t w)
 {
-    uint32_t r = 0;
-#pragma unroll
-    for (int e = 0; e < 8; ++e) r |= ((byte >> e) & 1u ? one : zero) << (4 * e);
-    return r;
+    return make_uint4(w & 0x11111111u, w & 0x22222222u, w & 0x44444444u, (w >> 1) & 0x44444444u);
 }
 
-__device__ __forceinline__ uint4 fp4_word(uint32_t w, const uint32_t *__restrict__ lut)
+// Per nibble: `one` where m has its bit 0 set, `minus` elsewhere (m holds
+// bit 0 of each nibble only, so m * 15 is a nibble mask without carries).
+__device__ __forceinline__ uint32_t fp4_select(uint32_t m, uint32_t one, uint32_t minus)
 {
-    return make_uint4(lut[w & 0xffu], lut[(w >> 8) & 0xffu], lut[(w >> 16) & 0xffu], lut[w >> 24]);
+    const uint32_t mask = m * 0xfu;
+    return (one & mask) | (minus & ~mask);
 }
 
-// Insert one key into a running top two (k1 >= k2): k2 = med3(k1, k2, key),
-// then k1 = max(k1, key), as one unit, so that only the current k1 is ever
-// live (the independent chains of the query blocks interleave; v_max_f32
-// written out, since the IEEE-mode fmaxf adds NaN quieting per operand).
-__device__ __forceinline__ void insert_key(float &k1, float &k2, float key)
+// Query word -> its four FP4 dwords (+-1 / c per bit: +-2, +-1, +-0.5, +-0.5).
+__device__ __forceinline__ uint4 fp4_query(uint32_t w)
 {
-    asm("v_med3_f32 %1, %0, %1, %2\n\t"
-        "v_max_f32 %0, %0, %2"
-        : "+v"(k1), "+v"(k2)
-        : "v"(key));
+    return make_uint4(fp4_select(w & 0x11111111u, 0x44444444u, 0xccccccccu),
+                      fp4_select((w >> 1) & 0x11111111u, 0x22222222u, 0xaaaaaaaau),
+                      fp4_select((w >> 2) & 0x11111111u, 0x11111111u, 0x99999999u),
+                      fp4_select((w >> 3) & 0x11111111u, 0x11111111u, 0x99999999u));
+}
+
+// Two keys into a running top two (k1 >= k2), as insert_pair_u32 does for
+// integer keys: t = med3(k1, x, y), k1 = max3(k1, x, y), k2 = max(k2, t), as
+// one unit (the independent chains of the query blocks interleave; the
+// instructions are written out, since the IEEE-mode fmaxf adds NaN quieting
+// per operand; keys are never NaN).
+__device__ __forceinline__ void insert_pair(float &k1, float &k2, float x, float y)
+{
+    float t;
+    asm("v_med3_f32 %2, %0, %3, %4\n\t"
+        "v_max3_f32 %0, %0, %3, %4\n\t"
+        "v_max_f32 %1, %1, %2"
+        : "+v"(k1), "+v"(k2), "=&v"(t)
+        : "v"(x), "v"(y));
 }
 
 __device__ __forceinline__ v8i fp4_operand(uint4 f)
@@ -411,13 +440,12 @@ __device__ __forceinline__ v8i fp4_operand(uint4 f)
 
 // Staging role of a thread: tile row tid % 32, packed words 2 (tid / 32) and
 // 2 (tid / 32) + 1, i.e. step tid / 32, both lane halves.
-__device__ __forceinline__ void stage_tile_fp4(uint2 w, int tid, const uint32_t *__restrict__ lut,
-                                               uint4 *__restrict__ buf)
+__device__ __forceinline__ void stage_tile_fp4(uint2 w, int tid, uint4 *__restrict__ buf)
 {
     const int r = tid & 31;
     const int s = tid >> 5;
-    buf[s * 64 + r] = fp4_word(w.x, lut);
-    buf[s * 64 + 32 + r] = fp4_word(w.y, lut);
+    buf[s * 64 + r] = fp4_train(w.x);
+    buf[s * 64 + 32 + r] = fp4_train(w.y);
 }
 
 // One (query group, train range) of the MXFP4 matcher.  Train rows
@@ -427,8 +455,7 @@ template <int QB>
 __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int nq,
                                          const uint32_t *__restrict__ train, int nt, int qgroup,
                                          int split, int split_rows, uint64_t (&best)[QB][2],
-                                         uint4 (*tbuf)[kFp4TileVec], const uint32_t *lut_train,
-                                         const uint32_t *lut_query)
+                                         uint4 (*tbuf)[kFp4TileVec])
 {
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -460,7 +487,7 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
         for (int s = 0; s < kFp4Steps; ++s) {
             const uint32_t w0 = qw[qb][2 * s], w1 = qw[qb][2 * s + 1];
             pc += __popc(w0) + __popc(w1);
-            bq[qb][s] = fp4_word(half ? w1 : w0, lut_query);
+            bq[qb][s] = fp4_query(half ? w1 : w0);
         }
         na[qb] = pc;
     }
@@ -476,7 +503,7 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     for (int r = 0; r < 16; ++r) c0[r] = (float)((1 << 14) - 1 - (8 * (r >> 2) + 4 * half + (r & 3)));
 
     __syncthreads();       // the staging buffers may still be read for a previous range
-    if (t_begin < t_end) stage_tile_fp4(ld0, tid, lut_train, tbuf[0]);
+    if (t_begin < t_end) stage_tile_fp4(ld0, tid, tbuf[0]);
     __syncthreads();
 
     // The MFMAs of one tile over LDS buffer `buf`.
@@ -492,7 +519,8 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
         }
     };
     // The top-2 update with one tile's keys: the running top two move into
-    // this tile's frame, then take the tile's 16 keys per query block.
+    // this tile's frame, then take the tile's 16 keys per query block, two
+    // at a time.
     auto tile_top2 = [&](const v16f (&acc)[QB]) {
 #pragma unroll
         for (int qb = 0; qb < QB; ++qb) {
@@ -500,9 +528,9 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
             k2[qb] += 32.0f;
         }
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
+        for (int r = 0; r < 16; r += 2) {
 #pragma unroll
-            for (int qb = 0; qb < QB; ++qb) insert_key(k1[qb], k2[qb], acc[qb][r]);
+            for (int qb = 0; qb < QB; ++qb) insert_pair(k1[qb], k2[qb], acc[qb][r], acc[qb][r + 1]);
         }
     };
     // Rows past nt (in the last tile only) take a key below every real one.
@@ -527,12 +555,12 @@ __device__ __forceinline__ void fp4_item(const uint32_t *__restrict__ query, int
     // empty keys up by 32 too, which keeps them below -2^24.)
     for (int tile = t_begin; tile < t_end; tile += 2) {
         tile_step(tile, 0);
-        stage_tile_fp4(ra, tid, lut_train, tbuf[1]);
+        stage_tile_fp4(ra, tid, tbuf[1]);
         ra = load_tile(train, nt, tile + 3, tid);
         __syncthreads();
         if (tile + 1 >= t_end) break;
         tile_step(tile + 1, 1);
-        stage_tile_fp4(rb, tid, lut_train, tbuf[0]);
+        stage_tile_fp4(rb, tid, tbuf[0]);
         rb = load_tile(train, nt, tile + 4, tid);
         __syncthreads();
     }
@@ -696,16 +724,11 @@ __global__ __launch_bounds__(kMfmaThreads) __attribute__((amdgpu_waves_per_eu(2,
 knn_fp4_kernel(SplitArgs a)
 {
     __shared__ uint4 tbuf[2][kFp4TileVec];
-    __shared__ uint32_t lut_train[256], lut_query[256];
-    lut_train[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0x0u);
-    lut_query[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0xau);
-    __syncthreads();
     const ItemOut direct{nullptr, a.idx, a.dist, a.accept, a.k, a.ratio};
     const ItemOut part{a.partial, nullptr, nullptr, nullptr, 2, 0.f};
     uint64_t best[QB][2];
     fp4_init_best(best);
-    fp4_item<QB>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows, best, tbuf,
-                 lut_train, lut_query);
+    fp4_item<QB>(a.query, a.nq, a.train, a.nt, blockIdx.x, blockIdx.y, a.split_rows, best, tbuf);
     fp4_store(best, a.nq, a.nt, blockIdx.x, blockIdx.y, a.nsplit == 1 ? direct : part);
 }
 
@@ -812,7 +835,6 @@ __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
                                            BatchState *__restrict__ st, int k, float ratio,
                                            int32_t *__restrict__ idx, int32_t *__restrict__ dist,
                                            uint8_t *__restrict__ accept, void *tbuf,
-                                           const uint32_t *lut_train, const uint32_t *lut_query,
                                            int *slot, int n_pairs)
 {
     for (;;) {
@@ -835,7 +857,7 @@ __device__ __forceinline__ void batch_loop(const uint32_t *__restrict__ query,
             const int ranges = max(1, (nt + (int)kFp4MaxSplitRows - 1) / (int)kFp4MaxSplitRows);
             for (int r = 0; r < ranges; ++r)
                 fp4_item<QB>(q, (int)e.nq, t, nt, qgroup, r, (int)kFp4MaxSplitRows, best,
-                             reinterpret_cast<uint4 (*)[kFp4TileVec]>(tbuf), lut_train, lut_query);
+                             reinterpret_cast<uint4 (*)[kFp4TileVec]>(tbuf));
             fp4_store(best, (int)e.nq, nt, qgroup, 0, out);
         } else {
             const int split_rows = max(kTileRows, (nt + kTileRows - 1) / kTileRows * kTileRows);
@@ -859,8 +881,7 @@ knn_batch_mfma_kernel(const uint32_t *__restrict__ query, const uint32_t *__rest
     __shared__ v4i tbuf[2][kTileVec];
     __shared__ int slot;
     batch_loop<BatchKind::kMfmaI8, kQueryBlocks>(query, train, pairs, info, item_pair, st, k, ratio,
-                                                 idx, dist, accept, tbuf, nullptr, nullptr, &slot,
-                                                 n_pairs);
+                                                 idx, dist, accept, tbuf, &slot, n_pairs);
 }
 
 template <int QB>
@@ -872,13 +893,9 @@ knn_batch_fp4_kernel(const uint32_t *__restrict__ query, const uint32_t *__restr
                      int32_t *__restrict__ dist, uint8_t *__restrict__ accept)
 {
     __shared__ uint4 tbuf[2][kFp4TileVec];
-    __shared__ uint32_t lut_train[256], lut_query[256];
     __shared__ int slot;
-    lut_train[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0x0u);
-    lut_query[threadIdx.x] = fp4_byte(threadIdx.x, 0x2u, 0xau);
-    __syncthreads();
     batch_loop<BatchKind::kMfmaFp4, QB>(query, train, pairs, info, item_pair, st, k, ratio, idx,
-                                        dist, accept, tbuf, lut_train, lut_query, &slot, n_pairs);
+                                        dist, accept, tbuf, &slot, n_pairs);
 }
 
 __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
@@ -889,7 +906,7 @@ __global__ __launch_bounds__(256) void knn_batch_popcount_kernel(
 {
     __shared__ int slot;
     batch_loop<BatchKind::kPopcount, 1>(query, train, pairs, info, item_pair, st, k, ratio, idx,
-                                        dist, accept, nullptr, nullptr, nullptr, &slot, n_pairs);
+                                        dist, accept, nullptr, &slot, n_pairs);
 }
 
 }  // namespace
