@@ -11,7 +11,8 @@
 // y with floor(y * bands / H) = b, bands = min(ceil(H / 32), 64):
 //   1. per image, the first bucket (one workgroup, an exclusive scan);
 //   2. the bucket counts are cleared;
-//   3. each keypoint takes its bucket and a rank in it (an atomic add);
+//   3. each keypoint takes its bucket and a rank in it (counted per chunk of
+//      keypoints in LDS, one global atomic add per chunk and bucket);
 //   4. the counts become first positions (one workgroup, an exclusive scan);
 //   5. each keypoint's index is written at its bucket's first position plus
 //      its rank.
@@ -90,29 +91,97 @@ __device__ __forceinline__ int64_t keypoint_count(int64_t n_host, const int64_t 
     return n;
 }
 
-// Step 3: bucket and rank of every keypoint.
+// Step 3: bucket and rank of every keypoint.  A workgroup takes a chunk of
+// kOrderChunk consecutive keypoints.  When the chunk's buckets span fewer
+// than kOrderChunk values (keypoints of one or two images, as a batch built
+// image by image has them) it counts them in LDS, ranking each keypoint
+// within the chunk, then takes one global atomic per bucket it touched for
+// the chunk's first rank there; otherwise every keypoint takes its rank with
+// a global atomic.
+constexpr int kOrderChunk = 4096;
+constexpr int kOrderPerThread = kOrderChunk / kOrderThreads;
+
+__device__ __forceinline__ int bucket_of(const float4 *__restrict__ kps,
+                                         const int32_t *__restrict__ image_id,
+                                         const ImageEntry *__restrict__ table, int n_images,
+                                         const int32_t *__restrict__ band_base, int64_t p)
+{
+    const int id = image_id[p];
+    int b = band_base[n_images];
+    if (id >= 0 && id < n_images) {
+        const ImageEntry e = table[id];
+        const float y = kps[p].y;
+        if (image_ok(e) && __builtin_isfinite(y)) {
+            const int bands = bands_of(e);
+            const int row = (int)fminf(fmaxf(floorf(y), 0.0f), (float)(e.height - 1));
+            b = band_base[id] + (int)((int64_t)row * bands / e.height);
+        }
+    }
+    return b;
+}
+
 __global__ __launch_bounds__(kOrderThreads) void order_count_kernel(
     const float4 *__restrict__ kps, const int32_t *__restrict__ image_id,
     const ImageEntry *__restrict__ table, int n_images, int64_t n_host,
     const int64_t *__restrict__ n_dev, const int32_t *__restrict__ band_base,
     int32_t *__restrict__ counts, int32_t *__restrict__ bucket, int32_t *__restrict__ rank)
 {
+    __shared__ int32_t hist[kOrderChunk];
+    __shared__ int32_t lo_s, hi_s;
     const int64_t n = keypoint_count(n_host, n_dev);
-    for (int64_t p = (int64_t)blockIdx.x * kOrderThreads + threadIdx.x; p < n;
-         p += (int64_t)gridDim.x * kOrderThreads) {
-        const int id = image_id[p];
-        int b = band_base[n_images];
-        if (id >= 0 && id < n_images) {
-            const ImageEntry e = table[id];
-            const float y = kps[p].y;
-            if (image_ok(e) && __builtin_isfinite(y)) {
-                const int bands = bands_of(e);
-                const int row = (int)fminf(fmaxf(floorf(y), 0.0f), (float)(e.height - 1));
-                b = band_base[id] + (int)((int64_t)row * bands / e.height);
+    const int64_t first = (int64_t)blockIdx.x * kOrderChunk;
+    if (first >= n) return;                       // uniform over the workgroup
+    const int t = threadIdx.x;
+    int b[kOrderPerThread];
+    int lo = 0x7fffffff, hi = -1;
+#pragma unroll
+    for (int i = 0; i < kOrderPerThread; ++i) {
+        const int64_t p = first + i * kOrderThreads + t;
+        b[i] = p < n ? bucket_of(kps, image_id, table, n_images, band_base, p) : -1;
+        if (b[i] >= 0) {
+            lo = min(lo, b[i]);
+            hi = max(hi, b[i]);
+        }
+    }
+    if (t == 0) {
+        lo_s = 0x7fffffff;
+        hi_s = -1;
+    }
+    __syncthreads();
+    atomicMin(&lo_s, lo);
+    atomicMax(&hi_s, hi);
+    __syncthreads();
+    const int base = lo_s, span = hi_s - lo_s + 1;    // the chunk has a keypoint: span >= 1
+    if (span > kOrderChunk) {
+#pragma unroll
+        for (int i = 0; i < kOrderPerThread; ++i) {
+            const int64_t p = first + i * kOrderThreads + t;
+            if (b[i] >= 0) {
+                bucket[p] = b[i];
+                rank[p] = atomicAdd(&counts[b[i]], 1);
             }
         }
-        bucket[p] = b;
-        rank[p] = atomicAdd(&counts[b], 1);
+        return;
+    }
+    for (int i = t; i < span; i += kOrderThreads) hist[i] = 0;
+    __syncthreads();
+    int r[kOrderPerThread];
+#pragma unroll
+    for (int i = 0; i < kOrderPerThread; ++i)
+        r[i] = b[i] >= 0 ? atomicAdd(&hist[b[i] - base], 1) : 0;
+    __syncthreads();
+    for (int i = t; i < span; i += kOrderThreads) {
+        const int c = hist[i];
+        if (c > 0) hist[i] = atomicAdd(&counts[base + i], c);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kOrderPerThread; ++i) {
+        const int64_t p = first + i * kOrderThreads + t;
+        if (b[i] >= 0) {
+            bucket[p] = b[i];
+            rank[p] = hist[b[i] - base] + r[i];
+        }
     }
 }
 
@@ -163,13 +232,14 @@ hipError_t launch_order(const ExtractArgs &a, uint8_t *ws, hipStream_t stream)
     const int64_t per_pass = (int64_t)a.num_cus * 8 * kOrderThreads;
     const unsigned grid_kps = (unsigned)min((a.n + kOrderThreads - 1) / kOrderThreads,
                                             per_pass / kOrderThreads);
+    const unsigned grid_chunks = (unsigned)((a.n + kOrderChunk - 1) / kOrderChunk);
     const unsigned grid_clear = (unsigned)min((l.max_buckets + kOrderThreads - 1) / kOrderThreads,
                                               per_pass / kOrderThreads);
     hipLaunchKernelGGL(order_bands_kernel, dim3(1), dim3(kOrderThreads), 0, stream, a.table,
                        a.n_images, band_base);
     hipLaunchKernelGGL(order_clear_kernel, dim3(grid_clear), dim3(kOrderThreads), 0, stream, counts,
                        l.max_buckets);
-    hipLaunchKernelGGL(order_count_kernel, dim3(grid_kps), dim3(kOrderThreads), 0, stream, a.kps,
+    hipLaunchKernelGGL(order_count_kernel, dim3(grid_chunks), dim3(kOrderThreads), 0, stream, a.kps,
                        a.image_id, a.table, a.n_images, a.n, a.n_dev, band_base, counts, bucket,
                        rank);
     hipLaunchKernelGGL(order_scan_kernel, dim3(1), dim3(kOrderThreads), 0, stream, band_base,

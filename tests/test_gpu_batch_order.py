@@ -152,3 +152,31 @@ def test_device_count_limits_the_order(torch_cuda, triplets):
         assert np.array_equal(full, want)
     finally:
         lat.close()
+
+
+def test_interleaved_tall_images(torch_cuda, triplets):
+    """100 images of 2048 rows (64 bands each), keypoints interleaved at random:
+    a chunk of consecutive keypoints spans more buckets than the per-chunk
+    LDS count holds, so ranks come from one global atomic per keypoint."""
+    torch = torch_cuda
+    from paper_1609_03986_amd.binding import Latch, image_table
+    g = np.random.default_rng(13)
+    sizes = [(2048, 24 + (i % 5)) for i in range(100)]
+    n = ORDER_MIN + 1234
+    imgs = [synth.smoothed_noise(g, h, w) for h, w in sizes]
+    ids = g.integers(0, len(sizes), n).astype(np.int32)
+    kps = np.zeros((n, 4), np.float32)
+    for i, (h, w) in enumerate(sizes):
+        sel = np.nonzero(ids == i)[0]
+        kps[sel] = synth.random_keypoints(g, len(sel), h, w, margin=-8)
+    dev_imgs = [torch.from_numpy(im).cuda() for im in imgs]
+    lat = Latch(triplets)
+    try:
+        got = lat.extract_batch(image_table(dev_imgs), len(sizes), torch.from_numpy(ids).cuda(),
+                                torch.from_numpy(kps).cuda())
+        torch.cuda.synchronize()
+        assert lat.check_errors(clear=True) == 0
+        want = single_calls(torch, lat, dev_imgs, kps, ids)
+        assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
+    finally:
+        lat.close()
