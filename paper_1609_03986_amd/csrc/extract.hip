@@ -3,14 +3,16 @@
 // A workgroup of two wavefronts computes one descriptor at a time
 // (grid-stride over keypoints):
 //   1. resampling rule steps 1-3 on the keypoint (uniform across the group);
-//   2. gather of the 48 x 48 upright window (steps 4-5).  The sample offsets
-//      of window positions (u, v), (-v, u), (-u, -v), (v, -u) are (ox, oy),
-//      (-oy, ox), (-ox, -oy), (oy, -ox): quarter turns of the same rounded
-//      pair, because the rounding is odd-symmetric.  So the 47 x 47 core is
-//      552 such orbits plus the centre, each costing one pair of roundings
-//      for four samples, and row 0 and column 0 (95 samples) are done one by
-//      one.  The byte loads are issued one keypoint ahead so that their
-//      latency overlaps the previous descriptor's arithmetic;
+//   2. gather of the 48 x 48 upright window (steps 4-5), one byte load per
+//      window position, 18 per thread.  The vector L1 serves a load one
+//      cache line at a time, so the positions are taken in an order that
+//      keeps each load's 64 samples on few lines: for the keypoint's angle
+//      class (32 bins), the positions sorted by the image row they sample at
+//      the class's middle angle, then by column (a host-built table).  A
+//      load then covers a band about 1.3 s image rows high (s the scale)
+//      instead of a block of window positions up to 8 s sqrt 2 rows high.
+//      The loads are issued one keypoint ahead so that their latency
+//      overlaps the previous descriptor's arithmetic;
 //   3. the samples are written to a plain window in LDS, and a copy pass
 //      builds eight byte-shifted copies of it in which every 7-byte patch
 //      row is one 8-byte-aligned quadword with a zero last byte;
@@ -41,23 +43,10 @@ namespace {
 constexpr int kThreads = kExtractWaves * 64;             // 128: two wavefronts per window
 constexpr int kRoundsPerWave = 8 / kExtractWaves;         // 4
 
-// Gather work per window: orbits with representative (u, v), u in [1, 23],
-// v in [0, 23], and single samples (row 0, column 0, the centre).
-constexpr int kOrbitU = kHalf - 1;                        // 23
-constexpr int kOrbits = kOrbitU * kHalf;                  // 552
-constexpr int kSingles = 2 * kWin;                        // 96 = 48 + 47 + 1
-constexpr int kFullSlots = 4;                             // orbit slots every thread has
-constexpr int kSlot4Orbits = kOrbits - kFullSlots * kThreads;     // 40 (threads 0..39)
-constexpr int kSlot4Singles = kThreads - kSlot4Orbits;            // 88 (threads 40..127)
-constexpr int kSlot5Singles = kSingles - kSlot4Singles;           // 8 (threads 0..7)
-constexpr int kSlots = kFullSlots + 2;
-constexpr int kSamples = 4 * (kFullSlots + 1) + 1;                // 21 bytes in flight per thread
-static_assert(kSlot4Orbits > 0 && kSlot4Orbits <= 64 && kSlot5Singles > 0 && kSlot5Singles <= 64,
-              "slot 4 orbits and slot 5 singles belong to wavefront 0");
-static_assert(4 * kOrbits + 1 + (kSingles - 1) == kWin * kWin, "every window byte once");
+// Gather slots per thread: window positions 128 m + tid of the gather order.
+constexpr int kGatherSlots = kWin * kWin / kThreads;      // 18
+static_assert(kGatherSlots * kThreads == kWin * kWin, "every window byte once");
 
-// Raw window byte of position (u, v): kRawBase + (v + 24) kRawStride + u + 24.
-constexpr int kRawCentre = kRawBase + kHalf * kRawStride + kHalf;
 // Copy pass: units (row y, quadword q), 240 per window, unit e = 5 y + q.
 constexpr int kCopyUnits = kWin * kCopyQwords;
 static_assert(kCopyUnits > kThreads && kCopyUnits <= 2 * kThreads, "two copy units per thread");
@@ -65,175 +54,55 @@ static_assert(kWinLdsBytes * 8 <= kLdsPerCu, "eight windows per CU");
 
 #include "keypoint.h"
 
-
-// This thread's gather slots.  Slot m < 4 is orbit tid + 128 m; slot 4 is
-// orbit 512 + tid (tid < 40) or single tid - 40; slot 5 is single 88 + tid
-// (tid < 8).  uv packs (u & 0xffff) | v << 16 of the representative
-// position; raw packs the raw-window byte addresses of its first two orbit
-// members (the other two are 2 kRawCentre minus these).
-struct Slots {
-    int uv[kSlots];
-    uint32_t raw[kSlots - 1];     // slot 5's is recomputed when written
-};
-
-__device__ __forceinline__ int pack_uv(int u, int v)
+// Raw-window byte of the position in half `h` of packed entry pair `d`.
+__device__ __forceinline__ uint32_t raw_of(uint32_t d, int h)
 {
-    return (u & 0xffff) | (v << 16);
+    const int u = __builtin_amdgcn_sbfe((int)d, 16 * h, 8);
+    const int v = __builtin_amdgcn_sbfe((int)d, 16 * h + 8, 8);
+    return (uint32_t)(kRawBase + kHalf * kRawStride + kHalf + mad_i24(v, kRawStride, u));
 }
 
-__device__ __forceinline__ uint32_t raw_addr(int u, int v)
-{
-    return (uint32_t)(kRawCentre + v * kRawStride + u);
-}
-
-// Orbit o -> representative (u, v), u in [1, 23], v in [0, 23], in 8 x 8
-// blocks (u 1..8, 9..16, 17..23 within each band of 8 v), so that the 64
-// lanes of one load instruction sample a compact patch of the image and
-// touch few cache lines whatever the rotation.
-__device__ __forceinline__ void orbit_slot(int o, int &uv, uint32_t &raw)
-{
-    constexpr int kBand = kOrbitU * 8;                    // 184 orbits per band of 8 rows
-    const int vb = o / kBand, r = o - kBand * vb;
-    int u, v;
-    if (r < 128) {
-        const int ub = r >> 6, i = r & 63;
-        u = 8 * ub + (i & 7) + 1;
-        v = 8 * vb + (i >> 3);
-    } else {
-        const int i = r - 128;                            // the 7-wide block, u 17..23
-        u = 17 + i % 7;
-        v = 8 * vb + i / 7;
-    }
-    uv = pack_uv(u, v);
-    raw = raw_addr(u, v) | (raw_addr(-v, u) << 16);
-}
-
-// Single s: row 0 (v = -24) for s < 48, column 0 (u = -24, v = -23..23) for
-// s < 95, the centre for s = 95.
-__device__ __forceinline__ void single_slot(int s, int &uv, uint32_t &raw)
-{
-    int u, v;
-    if (s < kWin) {
-        u = s - kHalf;
-        v = -kHalf;
-    } else if (s < kSingles - 1) {
-        u = -kHalf;
-        v = s - kWin - (kHalf - 1);
-    } else {
-        u = v = 0;
-    }
-    uv = pack_uv(u, v);
-    raw = raw_addr(u, v);
-}
-
-__device__ __forceinline__ Slots thread_slots(int tid)
-{
-    Slots sl;
-#pragma unroll
-    for (int m = 0; m < kFullSlots; ++m) orbit_slot(tid + kThreads * m, sl.uv[m], sl.raw[m]);
-    if (tid < kSlot4Orbits)
-        orbit_slot(kFullSlots * kThreads + tid, sl.uv[4], sl.raw[4]);
-    else
-        single_slot(tid - kSlot4Orbits, sl.uv[4], sl.raw[4]);
-    uint32_t unused;
-    single_slot(kSlot4Singles + min(tid, kSlot5Singles - 1), sl.uv[5], unused);
-    return sl;
-}
-
-// Rule step 4 for one position: the rounded offsets of (u, v).
+// Rule steps 4-5 for this thread's 18 positions of keypoint k: its entries of
+// the keypoint's angle class (three 16-byte loads; kept in e, two per dword,
+// for write_raw), the rounded offsets and the byte loads into g.
 // sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
 // sq <= 2^10, so every product is exact and full rate.
-__device__ __forceinline__ void offsets(const Keypoint &k, int uv, int &ox, int &oy)
+__device__ __forceinline__ void issue_gather(const Keypoint &k, const uint16_t *__restrict__ order,
+                                             int tid, uint32_t (&e)[kGatherSlots / 2],
+                                             uint32_t (&g)[kGatherSlots])
 {
-    const int u = (int)(short)(uv & 0xffff);
-    const int v = uv >> 16;
-    ox = round_q22(mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))));
-    oy = round_q22(mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
-}
-
-// Rule step 5 for the four members of an orbit: offsets (ox, oy), (-oy, ox),
-// (-ox, -oy), (oy, -ox) from the centre.  Members 1..3 are loaded only when
-// `whole` (slot 4 holds a single sample in some lanes: member 0 only).  The
-// members of a position with |u|, |v| <= 24 are positions of the same kind,
-// so the interior test covers all four.
-__device__ __forceinline__ void gather_orbit(const Keypoint &k, GlobalByte *img, int uv, bool whole,
-                                             uint32_t &g0, uint32_t &g1, uint32_t &g2, uint32_t &g3)
-{
-    int ox, oy;
-    offsets(k, uv, ox, oy);
-    uint32_t a0, a1, a2, a3;
-    if (k.interior) {
-        // Every sample is inside the image, so |offset| * pitch < 2^31 and the
-        // 24-bit multiply-adds are exact.
-        const int base = k.centre;
-        const int t = mad_i24_s(k.pitch, oy, ox);
-        const int w = mad_i24_s(k.pitch, ox, -oy);
-        a0 = (uint32_t)(base + t);
-        a1 = (uint32_t)(base + w);
-        a2 = (uint32_t)(base - t);
-        a3 = (uint32_t)(base - w);
-    } else {
-        const int xm = k.width - 1, ym = k.height - 1;
-        a0 = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
-        a1 = (uint32_t)mad_i24(clamp_med3(k.cy + ox, 0, ym), k.pitch, clamp_med3(k.cx - oy, 0, xm));
-        a2 = (uint32_t)mad_i24(clamp_med3(k.cy - oy, 0, ym), k.pitch, clamp_med3(k.cx - ox, 0, xm));
-        a3 = (uint32_t)mad_i24(clamp_med3(k.cy - ox, 0, ym), k.pitch, clamp_med3(k.cx + oy, 0, xm));
-    }
-    g0 = img[a0];
-    if (whole) {
-        g1 = img[a1];
-        g2 = img[a2];
-        g3 = img[a3];
-    }
-}
-
-__device__ __forceinline__ uint32_t gather_single(const Keypoint &k, GlobalByte *img, int uv)
-{
-    int ox, oy;
-    offsets(k, uv, ox, oy);
-    if (k.interior) return img[(uint32_t)(k.centre + mad_i24_s(k.pitch, oy, ox))];
-    const int x = clamp_med3(k.cx + ox, 0, k.width - 1);
-    const int y = clamp_med3(k.cy + oy, 0, k.height - 1);
-    return img[(uint32_t)mad_i24(y, k.pitch, x)];
-}
-
-// Issue this thread's byte loads for keypoint k (results land in g).
-__device__ __forceinline__ void issue_gather(const Keypoint &k, int tid, bool wave0, const Slots &sl,
-                                             uint32_t (&g)[kSamples])
-{
+    const uint4 *t = reinterpret_cast<const uint4 *>(
+        order + ((size_t)k.cls * kThreads + tid) * kGatherThreadEntries);
+    const uint4 t0 = t[0], t1 = t[1], t2 = t[2];
+    e[0] = t0.x, e[1] = t0.y, e[2] = t0.z, e[3] = t0.w;
+    e[4] = t1.x, e[5] = t1.y, e[6] = t1.z, e[7] = t1.w;
+    e[8] = t2.x;
     GlobalByte *img = (GlobalByte *)k.img;
+    const int xm = k.width - 1, ym = k.height - 1;
 #pragma unroll
-    for (int m = 0; m < kFullSlots; ++m)
-        gather_orbit(k, img, sl.uv[m], true, g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
-    gather_orbit(k, img, sl.uv[4], tid < kSlot4Orbits, g[16], g[17], g[18], g[19]);
-    if (wave0 && tid < kSlot5Singles) g[20] = gather_single(k, img, sl.uv[5]);
-}
-
-__device__ __forceinline__ void write_orbit(uint8_t *lds, uint32_t raw, bool whole, uint32_t g0,
-                                            uint32_t g1, uint32_t g2, uint32_t g3)
-{
-    const uint32_t r0 = raw & 0xffffu, r1 = raw >> 16;
-    lds[r0] = (uint8_t)g0;
-    if (whole) {
-        lds[r1] = (uint8_t)g1;
-        lds[2 * kRawCentre - r0] = (uint8_t)g2;
-        lds[2 * kRawCentre - r1] = (uint8_t)g3;
+    for (int m = 0; m < kGatherSlots; ++m) {
+        const int u = __builtin_amdgcn_sbfe((int)e[m >> 1], 16 * (m & 1), 8);
+        const int v = __builtin_amdgcn_sbfe((int)e[m >> 1], 16 * (m & 1) + 8, 8);
+        const int ox = round_q22(mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))));
+        const int oy = round_q22(mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
+        uint32_t a;
+        if (k.interior) {
+            // Every sample is inside the image, so |offset| * pitch < 2^31 and the
+            // 24-bit multiply-add is exact.
+            a = (uint32_t)(k.centre + mad_i24_s(k.pitch, oy, ox));
+        } else {
+            a = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
+        }
+        g[m] = img[a];
     }
 }
 
 // The gathered samples into the raw window.
-__device__ __forceinline__ void write_raw(uint8_t *lds, int tid, bool wave0, const Slots &sl,
-                                          const uint32_t (&g)[kSamples])
+__device__ __forceinline__ void write_raw(uint8_t *lds, const uint32_t (&e)[kGatherSlots / 2],
+                                          const uint32_t (&g)[kGatherSlots])
 {
 #pragma unroll
-    for (int m = 0; m < kFullSlots; ++m)
-        write_orbit(lds, sl.raw[m], true, g[4 * m], g[4 * m + 1], g[4 * m + 2], g[4 * m + 3]);
-    write_orbit(lds, sl.raw[4], tid < kSlot4Orbits, g[16], g[17], g[18], g[19]);
-    if (wave0 && tid < kSlot5Singles) {
-        // Slot 5's address is recomputed here rather than held in a register.
-        const int uv = sl.uv[5];
-        lds[raw_addr((int)(short)(uv & 0xffff), uv >> 16)] = (uint8_t)g[20];
-    }
+    for (int m = 0; m < kGatherSlots; ++m) lds[raw_of(e[m >> 1], m & 1)] = (uint8_t)g[m];
 }
 
 // Copy unit e = 5 y + q: from raw bytes (y, 8 q .. 8 q + 15) build the
@@ -351,14 +220,14 @@ template <bool kTable>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))) void extract_kernel(
     ImageSource src, const float4 *__restrict__ kps, int64_t n_host, const int64_t *__restrict__ n_dev,
     const int2 *__restrict__ rot, const uint2 *__restrict__ trip_off,
-    const uint32_t *__restrict__ unperm, uint32_t *__restrict__ desc, uint32_t *__restrict__ flags)
+    const uint32_t *__restrict__ unperm, const uint16_t *__restrict__ gather_order,
+    uint32_t *__restrict__ desc, uint32_t *__restrict__ flags)
 {
     __shared__ __attribute__((aligned(16))) uint8_t lds[kWinLdsBytes];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const bool wave0 = wave == 0;
 
     // Wavefront w evaluates triplets 256 w .. 256 w + 255 in 4 rounds; slot
     // 64 r + lane holds the triplet the bank-aware assignment put there, and
@@ -389,12 +258,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     // (slots >> 8 k) & 0xff of its wavefront (constant over keypoints).
     const uint32_t slots = unperm[64 * wave + lane];
     const int64_t stride = range.stride;
-    const Slots sl = thread_slots(tid);
-    uint32_t g[kSamples];
+    uint32_t e[kGatherSlots / 2], g[kGatherSlots];
     KeypointBatch batch = prepare_batch<kTable, kHalf>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
     Keypoint cur = batch_get<kTable>(batch, 0, src, &bad_image);
-    if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
+    if (cur.ok) issue_gather(cur, gather_order, tid, e, g);
 
     for (int i = 0; p < n; ++i, p += stride) {
         const bool compute = cur.ok;
@@ -407,7 +275,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         } else {
             // The raw window was last read by the previous descriptor's copy
             // pass, which ended before that descriptor's second barrier.
-            write_raw(lds, tid, wave0, sl, g);
+            write_raw(lds, e, g);
             __syncthreads();   // raw window complete; the previous triplet reads are done
             copy_unit(lds, tid);
             if (tid < kCopyUnits - kThreads) copy_unit(lds, tid + kThreads);
@@ -418,7 +286,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
         const int j = (i + 1) & 63;
         if (j == 0) batch = prepare_batch<kTable, kHalf>(kps, n, p + stride, stride, lane, rot, src);
         cur = batch_get<kTable>(batch, j, src, &bad_image);
-        if (cur.ok) issue_gather(cur, tid, wave0, sl, g);
+        if (cur.ok) issue_gather(cur, gather_order, tid, e, g);
         if (!compute) continue;
 
         // Eq. 1 for this wavefront's 256 triplets, in slot order.
@@ -459,10 +327,12 @@ hipError_t launch_extract(const ExtractArgs &a, hipStream_t stream)
     ImageSource src{a.img, a.height, a.width, a.pitch, a.table, a.image_id, a.n_images, a.order};
     if (a.table)
         hipLaunchKernelGGL(extract_kernel<true>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.desc, a.flags);
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.gather, a.desc,
+                           a.flags);
     else
         hipLaunchKernelGGL(extract_kernel<false>, dim3((unsigned)blocks), dim3(kThreads), 0, stream,
-                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.desc, a.flags);
+                           src, a.kps, a.n, a.n_dev, a.rot, a.trip_off, a.unperm, a.gather, a.desc,
+                           a.flags);
     return hipGetLastError();
 }
 

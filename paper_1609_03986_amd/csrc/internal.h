@@ -13,6 +13,13 @@ constexpr int kPatchR = 3;               // 7 x 7 patches
 constexpr int kTriplets = 512;
 constexpr int kWords = 16;
 constexpr int kBins = 4096;
+// Window gather order: per angle class (32 bins), the window positions in
+// bands of a quarter image row at unit scale, each band by image column
+// (host-built); for each of the 128 extraction threads its 18 positions
+// (entries 128 m + thread) as 16-bit entries u & 0xff | (v & 0xff) << 8,
+// padded to 24 so that a thread reads them with three 16-byte loads.
+constexpr int kGatherClasses = kBins / 32;
+constexpr int kGatherThreadEntries = 24;
 
 // Extraction LDS layout, per workgroup.
 //  * Copies s = 0..7: copy s holds, for every window row y and quadword
@@ -76,6 +83,7 @@ struct ExtractArgs {
     const int2 *rot;          // [4096] {cos_q14, sin_q14}
     const uint2 *trip_off;    // [512] by slot: {offA | off1 << 16, off2} LDS byte offsets
     const uint32_t *unperm;   // [128] per (wavefront, lane): slots of its four output bits
+    const uint16_t *gather;   // [kGatherClasses][128][kGatherThreadEntries] gather order
     uint32_t *desc;
     uint32_t *flags;
     int num_cus;

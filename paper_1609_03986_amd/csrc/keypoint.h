@@ -106,6 +106,7 @@ struct Keypoint {
     bool interior;  // every sample lies inside the image: no clamping needed
     int cx, cy;
     int c, s, sq;   // C[b], S[b] (Q14) and the Q8 scale
+    int cls;        // angle class b >> 5 (0..127), which orders the window gather
     const uint8_t *img;
     int height, width, pitch;
     int centre;     // cy * pitch + cx (meaningful when interior)
@@ -130,7 +131,7 @@ struct ImageSource {
 struct KeypointBatch {
     int cx, cy;
     int cs;          // C[b] & 0xffff | S[b] << 16
-    int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18
+    int sq_flags;    // sq | ok << 16 | interior << 17 | bad image << 18 | (b >> 5) << 19
     int id;          // image table: the keypoint's image (0 when out of range)
     int key;         // keypoint index (the position itself without an order)
 };
@@ -187,7 +188,8 @@ __device__ __forceinline__ KeypointBatch prepare_batch(const float4 *__restrict_
     kb.cx = cx;
     kb.cy = cy;
     kb.cs = (cs.x & 0xffff) | (cs.y << 16);
-    kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18);
+    kb.sq_flags = sq | ((int)ok << 16) | ((int)interior << 17) | ((int)(real && !image_ok) << 18) |
+                  ((bin >> 5) << 19);
     kb.id = image_id;
     kb.key = (int)idx;
     return kb;
@@ -209,6 +211,7 @@ __device__ __forceinline__ Keypoint batch_get(const KeypointBatch &kb, int j, co
     k.ok = (f >> 16) & 1;
     k.interior = (f >> 17) & 1;
     *bad_image = (f >> 18) & 1;
+    k.cls = f >> 19;
     if (kTable) {
         // The keypoint's image entry, a uniform (scalar) load; the entry was
         // validated per lane in prepare_batch, and ok is false otherwise.

@@ -5,6 +5,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <algorithm>
 #include <array>
 #include <map>
 #include <mutex>
@@ -21,6 +22,7 @@ struct latch_ctx {
     int2 *rot_dev = nullptr;           // [4096] {cos_q14, sin_q14}
     uint2 *trip_off_dev = nullptr;     // [512] by slot: LDS byte offsets of the three patches
     uint32_t *unperm_dev = nullptr;    // [128] output-bit slots per (wavefront, lane)
+    uint16_t *gather_dev = nullptr;    // [kGatherClasses][128][24] window gather order
     uint32_t *flags_dev = nullptr;     // sticky error word
     // Weighted geometry (latch_create_geometry); window 0 runs the default kernel.
     int window = 0;
@@ -83,6 +85,44 @@ void rotation_table(int16_t *c, int16_t *s)
         c[a] = (int16_t)(-s[a - 1024]);
         s[a] = c[a - 1024];
     }
+}
+
+// Gather order of the extraction kernel.  For angle class c (bins 32 c ..
+// 32 c + 31), with (C, S) the cosine and sine of the class's middle angle,
+// window position (u, v) samples image row offset about s (S u + C v) and
+// column offset s (C u - S v) at scale s.  The positions are sorted by band
+// floor(4 (S u + C v)) (a quarter row at unit scale), then by column offset
+// (ties by position), so that the four lanes of a quad, which the vector L1
+// serves together, and the 64 lanes of a load fall on few cache lines.
+// Sorted entry k goes to thread k % 128, slot k / 128 (a wavefront's load m
+// takes 64 consecutive entries).  Entry: u & 0xff | (v & 0xff) << 8.
+std::vector<uint16_t> gather_order()
+{
+    constexpr int kPositions = kWin * kWin, kThreads = 2 * 64;
+    std::vector<uint16_t> table((size_t)kGatherClasses * kThreads * kGatherThreadEntries, 0);
+    std::vector<int> idx(kPositions);
+    std::vector<double> row(kPositions), col(kPositions);
+    for (int c = 0; c < kGatherClasses; ++c) {
+        const double a = 2.0 * M_PI * (32.0 * c + 16.0) / kBins;
+        const double cs = std::cos(a), sn = std::sin(a);
+        for (int p = 0; p < kPositions; ++p) {
+            const int u = p % kWin - kHalf, v = p / kWin - kHalf;
+            idx[p] = p;
+            row[p] = std::floor(4.0 * (sn * u + cs * v));
+            col[p] = cs * u - sn * v;
+        }
+        std::sort(idx.begin(), idx.end(), [&](int x, int y) {
+            if (row[x] != row[y]) return row[x] < row[y];
+            if (col[x] != col[y]) return col[x] < col[y];
+            return x < y;
+        });
+        for (int k = 0; k < kPositions; ++k) {
+            const int p = idx[k], u = p % kWin - kHalf, v = p / kWin - kHalf;
+            table[((size_t)c * kThreads + k % kThreads) * kGatherThreadEntries + k / kThreads] =
+                (uint16_t)((u & 0xff) | ((v & 0xff) << 8));
+        }
+    }
+    return table;
 }
 
 // LDS byte offset of the top-left byte of the 7 x 7 patch centred on (r, c):
@@ -439,6 +479,7 @@ ExtractArgs batch_extract_args(latch_handle h, const latch_image *images_dev, in
     a.rot = h->rot_dev;
     a.trip_off = h->trip_off_dev;
     a.unperm = h->unperm_dev;
+    a.gather = h->gather_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
@@ -658,14 +699,18 @@ int latch_create(latch_handle *out, const uint8_t *triplets_host)
         doff[t] = make_uint2(dense_patch_offset(tr[0], tr[1]) | (dense_patch_offset(tr[2], tr[3]) << 16),
                              dense_patch_offset(tr[4], tr[5]));
     }
+    const std::vector<uint16_t> order = gather_order();
+    const size_t order_bytes = order.size() * sizeof(uint16_t);
     hipError_t e;
     if ((e = hipMalloc((void **)&h->trip_off_dev, sizeof toff_slot)) == hipSuccess &&
         (e = hipMalloc((void **)&h->unperm_dev, sizeof unperm)) == hipSuccess &&
-        (e = hipMalloc((void **)&h->dense_off_dev, sizeof doff)) == hipSuccess) {
-        const Upload u[3] = {{h->dense_off_dev, doff, sizeof doff},
+        (e = hipMalloc((void **)&h->dense_off_dev, sizeof doff)) == hipSuccess &&
+        (e = hipMalloc((void **)&h->gather_dev, order_bytes)) == hipSuccess) {
+        const Upload u[4] = {{h->dense_off_dev, doff, sizeof doff},
                              {h->trip_off_dev, toff_slot, sizeof toff_slot},
-                             {h->unperm_dev, unperm, sizeof unperm}};
-        e = upload(u, 3);
+                             {h->unperm_dev, unperm, sizeof unperm},
+                             {h->gather_dev, order.data(), order_bytes}};
+        e = upload(u, 4);
     }
     if (e != hipSuccess) {
         rc = e == hipErrorOutOfMemory ? LATCH_ENOMEM : LATCH_EDEVICE;
@@ -755,6 +800,7 @@ void latch_destroy(latch_handle h)
     if (h->rot_dev) (void)hipFree(h->rot_dev);
     if (h->trip_off_dev) (void)hipFree(h->trip_off_dev);
     if (h->unperm_dev) (void)hipFree(h->unperm_dev);
+    if (h->gather_dev) (void)hipFree(h->gather_dev);
     if (h->flags_dev) (void)hipFree(h->flags_dev);
     if (h->wtrip_dev) (void)hipFree(h->wtrip_dev);
     if (h->wunperm_dev) (void)hipFree(h->wunperm_dev);
@@ -796,6 +842,7 @@ int latch_extract(latch_handle h, const uint8_t *img_dev, int height, int width,
     a.rot = h->rot_dev;
     a.trip_off = h->trip_off_dev;
     a.unperm = h->unperm_dev;
+    a.gather = h->gather_dev;
     a.desc = desc_dev;
     a.flags = h->flags_dev;
     a.num_cus = h->num_cus;
