@@ -308,7 +308,9 @@ int latch_detect(latch_handle h, const uint8_t *img_dev, int height, int width, 
  *              index -1 and distance 513.
  *   accept_dev: uint8[nq] or NULL: 1 iff nt >= 2 and d1 < ratio * d2, evaluated
  *              exactly (the second neighbour is always searched, also for k = 1).
- *   path:      a latch_path value; every path returns identical results.
+ *   path:      a latch_path value; every path returns identical results.  With more
+ *              than 65,535 x 16,384 train rows the MXFP4 path (whose keys hold a
+ *              14-bit split-local index) runs the int8 MFMA kernel instead.
  * nq == 0 is a no-op.  nq and nt must be < 2^31.  The train rows are split
  * over workgroups; with more than one split a merge kernel follows and the
  * partials live in the handle's workspace (hamming_knn_workspace_size;

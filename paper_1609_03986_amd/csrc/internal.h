@@ -50,6 +50,7 @@ constexpr int kLdsPerCu = 160 * 1024;                      // gfx950
 constexpr int kTileRows = 32;                    // train rows per MFMA tile
 constexpr int kTileBytes = kTileRows * 512;      // expanded tile: 16 steps x 64 lanes x 16 B
 constexpr int kMaxSplitRows = (1 << 21) - 32;    // split-local train index < 2^21 - 1
+constexpr int64_t kMaxSplits = 65535;            // train splits of a single-pair call (grid y)
 constexpr uint64_t kNoNeighbour = ~0ull;         // partial-result sentinel
 
 // Sticky error-word bits (same values as the LATCH_FLAG_* of the C ABI).

@@ -392,11 +392,22 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
     const int64_t max_rows = path == LATCH_PATH_MFMA_FP4 ? kFp4MaxSplitRows : kMaxSplitRows;
     const int64_t min_by_index = (nt + max_rows - 1) / max_rows;
     if (nsplit < min_by_index) nsplit = min_by_index;
-    if (nsplit > 65535) nsplit = 65535;
+    if (nsplit > kMaxSplits) nsplit = kMaxSplits;
     const int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
     p.split_rows = tiles_per_split * kTileRows;
     p.nsplit = (int)((tiles + tiles_per_split - 1) / tiles_per_split);
     return p;
+}
+
+// The split kernel a single-pair call runs: LATCH_PATH_AUTO resolved by the
+// tuning table, and the MXFP4 path, whose keys hold a 14-bit split-local
+// index, replaced by the int8 one (identical results) when the train rows
+// would need more than the 65,535 splits a grid dimension allows.
+int resolve_path(latch_handle h, int path, int64_t nq, int64_t nt)
+{
+    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+    if (path == LATCH_PATH_MFMA_FP4 && nt > kMaxSplits * kFp4MaxSplitRows) path = LATCH_PATH_MFMA;
+    return path;
 }
 
 // Partial top-2 keys of a split plan: 16 bytes per (split, query).
@@ -598,7 +609,7 @@ int knn_call(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32
     if (nq == 0) return LATCH_OK;
     if (!query_dev || !idx_dev || !dist_dev || (nt > 0 && !train_dev))
         return fail(h, LATCH_EINVAL, "null buffer");
-    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+    path = resolve_path(h, path, nq, nt);
 
     KnnSplitArgs a;
     a.query = query_dev;
@@ -1001,7 +1012,7 @@ int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path,
                     (long long)nt);
     if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
         return fail(h, LATCH_EINVAL, "unknown path %d", path);
-    if (path == LATCH_PATH_AUTO) path = h->tuning.path[size_bucket(nq)][size_bucket(nt)];
+    path = resolve_path(h, path, nq, nt);
     *bytes = nq == 0 ? 0 : knn_workspace_bytes(plan_knn(nq, nt, path, h->num_cus, h->tuning));
     return LATCH_OK;
 }
