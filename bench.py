@@ -500,6 +500,17 @@ def main():
         reps = max(3, args.steps // 2)
         u_plan, _ = timer.loop(ub.run_plan, reps, 2)
         u_plain, _ = timer.loop(u_run, reps, 1)
+        ub.close()
+        # The same plan captured under the library's default tuning table.
+        tuned = lat.get_tuning()
+        fresh = Latch(trip)
+        lat.set_tuning(fresh.get_tuning())
+        fresh.close()
+        ub_default = Batch(torch, lat, u_imgs, u_kps, args.path)
+        u_plan_default, _ = timer.loop(ub_default.run_plan, reps, 2)
+        ub_default.close()
+        lat.set_tuning(tuned)
+        del ub_default
         components["uneven_batch"] = {
             "workload": "256 images, sizes uniform over {320x240, 640x480, 1280x720, 1920x1080, "
                         "4000x3000}, keypoints round(LogNormal(ln 5000, 1)) clipped to "
@@ -507,8 +518,9 @@ def main():
             "descriptors": ub.total, "pairs": ub.n_pairs,
             "plan_ms": u_plan / reps * 1e3, "plain_form_ms": u_plain / reps * 1e3,
             "plan_speedup": u_plain / u_plan, "plan_desc_per_s": ub.total / (u_plan / reps),
-            "plan_pairs_per_s": ub.n_pairs / (u_plan / reps), "identical": bool(u_same)}
-        ub.close()
+            "plan_pairs_per_s": ub.n_pairs / (u_plan / reps), "identical": bool(u_same),
+            "tuning": tuning["source"],
+            "plan_ms_library_default_tuning": u_plan_default / reps * 1e3}
         del ub, u_out, u_run, u_imgs, u_kps
         torch.cuda.empty_cache()
 

@@ -180,3 +180,57 @@ def test_interleaved_tall_images(torch_cuda, triplets):
         assert np.array_equal(got.cpu().numpy().view(np.uint32), want)
     finally:
         lat.close()
+
+
+def test_plan_with_order_and_device_count(torch_cuda, triplets):
+    """A captured plan over 2^18 + 3,000 keypoints (so the order runs inside the
+    graph) replayed with the full count, a smaller one and the full one again:
+    descriptors equal the single-image calls up to the count and are untouched
+    past it, and matches equal eager batched matching of those descriptors."""
+    torch = torch_cuda
+    from paper_1609_03986_amd.binding import Latch, image_table, pair_table
+    g = np.random.default_rng(14)
+    sizes = [(1200, 1600), (900, 1000), (1500, 700)]
+    counts = [100_000, 90_000, ORDER_MIN + 3000 - 190_000]
+    imgs = [synth.smoothed_noise(g, h, w) for h, w in sizes]
+    kps = np.concatenate([synth.random_keypoints(g, n, h, w, margin=-8)
+                          for (h, w), n in zip(sizes, counts)]).astype(np.float32)
+    ids = np.repeat(np.arange(3, dtype=np.int32), counts)
+    n = len(kps)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]]).astype(np.int64)
+    pairs_np = np.array([(first[i], counts[i], first[i + 1], counts[i + 1], first[i])
+                         for i in range(2)], np.int64)
+    dev_imgs = [torch.from_numpy(im).cuda() for im in imgs]
+    lat = Latch(triplets)
+    try:
+        table = image_table(dev_imgs)
+        k = torch.from_numpy(kps).cuda()
+        idt = torch.from_numpy(ids).cuda()
+        nk = torch.tensor([n], dtype=torch.int64, device="cuda")
+        desc = torch.full((n, 16), SENTINEL, dtype=torch.int32, device="cuda")
+        idx = torch.full((n, 2), -7, dtype=torch.int32, device="cuda")
+        dist = torch.full((n, 2), -7, dtype=torch.int32, device="cuda")
+        acc = torch.full((n,), 9, dtype=torch.uint8, device="cuda")
+        pairs = pair_table(pairs_np)
+        plan = lat.plan(table, 3, idt, k, desc, pairs, idx, dist, acc, n_kps=nk)
+        want = single_calls(torch, lat, dev_imgs, kps, ids)
+        try:
+            for count in (n, n - 50_001, n):
+                nk.fill_(count)
+                desc.fill_(SENTINEL)
+                plan.run()
+                torch.cuda.synchronize()
+                got = desc.cpu().numpy().view(np.uint32)
+                assert np.array_equal(got[:count], want[:count])
+                assert np.all(got[count:] == 0xAAAAAAAA)
+            # The last replay matched the whole set: same as eager batched matching.
+            e_idx, e_dist, e_acc = lat.knn_batch(desc, desc, pairs, n)
+            torch.cuda.synchronize()
+            q = counts[0] + counts[1]                 # the query rows of the two pairs
+            assert torch.equal(idx[:q], e_idx[:q]) and torch.equal(dist[:q], e_dist[:q])
+            assert torch.equal(acc[:q], e_acc[:q])
+            assert lat.check_errors(clear=True) == 0
+        finally:
+            plan.close()
+    finally:
+        lat.close()
