@@ -4,15 +4,18 @@
 // (grid-stride over keypoints):
 //   1. resampling rule steps 1-3 on the keypoint (uniform across the group);
 //   2. gather of the 48 x 48 upright window (steps 4-5), one byte load per
-//      window position, 18 per thread.  The vector L1 serves a load one
-//      cache line at a time, so the positions are taken in an order that
-//      keeps each load's 64 samples on few lines: for the keypoint's angle
-//      class (32 bins), the positions sorted by the image row they sample at
-//      the class's middle angle, then by column (a host-built table).  A
-//      load then covers a band about 1.3 s image rows high (s the scale)
-//      instead of a block of window positions up to 8 s sqrt 2 rows high.
-//      The loads are issued one keypoint ahead so that their latency
-//      overlaps the previous descriptor's arithmetic;
+//      window position.  Rounding half away from zero is odd, so positions
+//      (u, v) and (-u, -v) sample at offsets (ox, oy) and (-ox, -oy): a thread
+//      rounds once for each of its 10 position pairs (over [-24, 24]^2; the
+//      extra row and column are gathered and not read).  The vector L1 serves
+//      a load one cache line at a time, so the pairs are taken in an order
+//      that keeps each load's 64 samples on few lines: for the keypoint's
+//      angle class (32 bins), sorted by the band of image rows their first
+//      member samples at the class's middle angle, then by column (a
+//      host-built table).  A load then covers a band about s image rows high
+//      (s the scale), its mirrored loads the mirrored band.  The loads are
+//      issued one keypoint ahead so that their latency overlaps the previous
+//      descriptor's arithmetic;
 //   3. the samples are written to a plain window in LDS, and a copy pass
 //      builds eight byte-shifted copies of it in which every 7-byte patch
 //      row is one 8-byte-aligned quadword with a zero last byte;
@@ -43,9 +46,11 @@ namespace {
 constexpr int kThreads = kExtractWaves * 64;             // 128: two wavefronts per window
 constexpr int kRoundsPerWave = 8 / kExtractWaves;         // 4
 
-// Gather slots per thread: window positions 128 m + tid of the gather order.
-constexpr int kGatherSlots = kWin * kWin / kThreads;      // 18
-static_assert(kGatherSlots * kThreads == kWin * kWin, "every window byte once");
+// Gather slots per thread: position pairs 128 m + tid of the gather order,
+// two samples each.
+constexpr int kGatherSlots = kGatherPairs;                // 10
+constexpr int kRawCentre = kRawBase + kHalf * kRawStride + kHalf;
+static_assert(kGatherSlots * kThreads >= ((kWin + 1) * (kWin + 1) + 1) / 2, "every pair once");
 
 // Copy pass: units (row y, quadword q), 240 per window, unit e = 5 y + q.
 constexpr int kCopyUnits = kWin * kCopyQwords;
@@ -54,29 +59,31 @@ static_assert(kWinLdsBytes * 8 <= kLdsPerCu, "eight windows per CU");
 
 #include "keypoint.h"
 
-// Raw-window byte of the position in half `h` of packed entry pair `d`.
+// Raw-window byte of the position in half `h` of packed entry pair `d` (the
+// first member of its pair; the second is at 2 kRawCentre minus it).
 __device__ __forceinline__ uint32_t raw_of(uint32_t d, int h)
 {
     const int u = __builtin_amdgcn_sbfe((int)d, 16 * h, 8);
     const int v = __builtin_amdgcn_sbfe((int)d, 16 * h + 8, 8);
-    return (uint32_t)(kRawBase + kHalf * kRawStride + kHalf + mad_i24(v, kRawStride, u));
+    return (uint32_t)(kRawCentre + mad_i24(v, kRawStride, u));
 }
 
-// Rule steps 4-5 for this thread's 18 positions of keypoint k: its entries of
-// the keypoint's angle class (three 16-byte loads; kept in e, two per dword,
-// for write_raw), the rounded offsets and the byte loads into g.
+// Rule steps 4-5 for this thread's 10 position pairs of keypoint k: its
+// entries of the keypoint's angle class (two 16-byte loads; kept in e, two
+// per dword, for write_raw), one pair of rounded offsets per position pair
+// (rounding half away from zero is odd: (-u, -v) samples at (-ox, -oy)), and
+// the byte loads of both members into g[2 m] and g[2 m + 1].
 // sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
 // sq <= 2^10, so every product is exact and full rate.
 __device__ __forceinline__ void issue_gather(const Keypoint &k, const uint16_t *__restrict__ order,
                                              int tid, uint32_t (&e)[kGatherSlots / 2],
-                                             uint32_t (&g)[kGatherSlots])
+                                             uint32_t (&g)[2 * kGatherSlots])
 {
     const uint4 *t = reinterpret_cast<const uint4 *>(
         order + ((size_t)k.cls * kThreads + tid) * kGatherThreadEntries);
-    const uint4 t0 = t[0], t1 = t[1], t2 = t[2];
+    const uint4 t0 = t[0], t1 = t[1];
     e[0] = t0.x, e[1] = t0.y, e[2] = t0.z, e[3] = t0.w;
-    e[4] = t1.x, e[5] = t1.y, e[6] = t1.z, e[7] = t1.w;
-    e[8] = t2.x;
+    e[4] = t1.x;
     GlobalByte *img = (GlobalByte *)k.img;
     const int xm = k.width - 1, ym = k.height - 1;
 #pragma unroll
@@ -85,24 +92,32 @@ __device__ __forceinline__ void issue_gather(const Keypoint &k, const uint16_t *
         const int v = __builtin_amdgcn_sbfe((int)e[m >> 1], 16 * (m & 1) + 8, 8);
         const int ox = round_q22(mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))));
         const int oy = round_q22(mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
-        uint32_t a;
+        uint32_t a0, a1;
         if (k.interior) {
             // Every sample is inside the image, so |offset| * pitch < 2^31 and the
             // 24-bit multiply-add is exact.
-            a = (uint32_t)(k.centre + mad_i24_s(k.pitch, oy, ox));
+            const int d = mad_i24_s(k.pitch, oy, ox);
+            a0 = (uint32_t)(k.centre + d);
+            a1 = (uint32_t)(k.centre - d);
         } else {
-            a = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
+            a0 = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
+            a1 = (uint32_t)mad_i24(clamp_med3(k.cy - oy, 0, ym), k.pitch, clamp_med3(k.cx - ox, 0, xm));
         }
-        g[m] = img[a];
+        g[2 * m] = img[a0];
+        g[2 * m + 1] = img[a1];
     }
 }
 
 // The gathered samples into the raw window.
 __device__ __forceinline__ void write_raw(uint8_t *lds, const uint32_t (&e)[kGatherSlots / 2],
-                                          const uint32_t (&g)[kGatherSlots])
+                                          const uint32_t (&g)[2 * kGatherSlots])
 {
 #pragma unroll
-    for (int m = 0; m < kGatherSlots; ++m) lds[raw_of(e[m >> 1], m & 1)] = (uint8_t)g[m];
+    for (int m = 0; m < kGatherSlots; ++m) {
+        const uint32_t r = raw_of(e[m >> 1], m & 1);
+        lds[r] = (uint8_t)g[2 * m];
+        lds[2 * kRawCentre - r] = (uint8_t)g[2 * m + 1];
+    }
 }
 
 // Copy unit e = 5 y + q: from raw bytes (y, 8 q .. 8 q + 15) build the
@@ -258,7 +273,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     // (slots >> 8 k) & 0xff of its wavefront (constant over keypoints).
     const uint32_t slots = unperm[64 * wave + lane];
     const int64_t stride = range.stride;
-    uint32_t e[kGatherSlots / 2], g[kGatherSlots];
+    uint32_t e[kGatherSlots / 2], g[2 * kGatherSlots];
     KeypointBatch batch = prepare_batch<kTable, kHalf>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
     Keypoint cur = batch_get<kTable>(batch, 0, src, &bad_image);

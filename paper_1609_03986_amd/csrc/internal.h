@@ -13,13 +13,16 @@ constexpr int kPatchR = 3;               // 7 x 7 patches
 constexpr int kTriplets = 512;
 constexpr int kWords = 16;
 constexpr int kBins = 4096;
-// Window gather order: per angle class (32 bins), the window positions in
-// bands of a quarter image row at unit scale, each band by image column
-// (host-built); for each of the 128 extraction threads its 18 positions
-// (entries 128 m + thread) as 16-bit entries u & 0xff | (v & 0xff) << 8,
-// padded to 24 so that a thread reads them with three 16-byte loads.
+// Window gather order: per angle class (32 bins), pairs of window positions
+// (u, v), (-u, -v) over [-24, 24]^2 (1,200 pairs and the centre), sorted by
+// the band of a quarter image row at unit scale of the first, then by its
+// image column (host-built); for each of the 128 extraction threads its 10
+// pairs (entries 128 m + thread; the last slots repeat the centre) as 16-bit
+// entries u & 0xff | (v & 0xff) << 8, padded to 16 so that a thread reads
+// them with two 16-byte loads.
 constexpr int kGatherClasses = kBins / 32;
-constexpr int kGatherThreadEntries = 24;
+constexpr int kGatherPairs = 10;
+constexpr int kGatherThreadEntries = 16;
 
 // Extraction LDS layout, per workgroup.
 //  * Copies s = 0..7: copy s holds, for every window row y and quadword
@@ -32,7 +35,9 @@ constexpr int kGatherThreadEntries = 24;
 //    The two interleave without overlap, so all patch rows share the row
 //    stride kCopyRowBytes.
 //  * The plain window, 48 rows of kRawStride bytes (13 dwords per row, so
-//    the lanes of a column-wise byte write fall in distinct banks).
+//    the lanes of a column-wise byte write fall in distinct banks), and a
+//    49th row and column that the gather fills and nothing reads (it samples
+//    positions in pairs (u, v), (-u, -v) over [-24, 24]^2).
 constexpr int kCopies = 8;
 constexpr int kCopyQwords = 5;
 constexpr int kCopyRowBytes = 8 * kCopyQwords;                     // 40
@@ -41,8 +46,8 @@ constexpr int kEdgeBase = kCopies * kCopyBytes;                    // 15360
 constexpr int kEdgeBytes = kCopyBytes + 8;                         // 1928
 constexpr int kRawBase = (kEdgeBase + kEdgeBytes + 15) / 16 * 16;  // 17296
 constexpr int kRawStride = 52;
-constexpr int kBallotBase = kRawBase + kWin * kRawStride;          // 19792: 8 ballot words per wavefront
-constexpr int kWinLdsBytes = kBallotBase + 2 * 8 * 4;              // 19856 per workgroup
+constexpr int kBallotBase = kRawBase + (kWin + 1) * kRawStride;    // 19844: 8 ballot words per wavefront
+constexpr int kWinLdsBytes = kBallotBase + 2 * 8 * 4;              // 19908 per workgroup
 constexpr int kExtractWaves = 2;                           // wavefronts per workgroup
 constexpr int kLdsPerCu = 160 * 1024;                      // gfx950
 

@@ -87,26 +87,37 @@ void rotation_table(int16_t *c, int16_t *s)
     }
 }
 
-// Gather order of the extraction kernel.  For angle class c (bins 32 c ..
-// 32 c + 31), with (C, S) the cosine and sine of the class's middle angle,
-// window position (u, v) samples image row offset about s (S u + C v) and
-// column offset s (C u - S v) at scale s.  The positions are sorted by band
-// floor(4 (S u + C v)) (a quarter row at unit scale), then by column offset
-// (ties by position), so that the four lanes of a quad, which the vector L1
-// serves together, and the 64 lanes of a load fall on few cache lines.
-// Sorted entry k goes to thread k % 128, slot k / 128 (a wavefront's load m
-// takes 64 consecutive entries).  Entry: u & 0xff | (v & 0xff) << 8.
+// Gather order of the extraction kernel.  Rounding half away from zero is
+// odd, so positions (u, v) and (-u, -v) sample at offsets (ox, oy) and
+// (-ox, -oy): the kernel rounds once per pair.  Over [-24, 24]^2 (the
+// window and one more row and column, which nothing reads) that is 1,200
+// pairs, taken with first member (u, v) with v > 0, or v = 0 and u > 0, plus
+// the centre.  For angle class c (bins 32 c .. 32 c + 31), with (C, S) the
+// cosine and sine of the class's middle angle, position (u, v) samples image
+// row offset about s (S u + C v) and column offset s (C u - S v) at scale s.
+// Pairs are sorted by the band floor(4 (S u + C v)) of their first member (a
+// quarter row at unit scale), then by its column offset (ties by position):
+// the four lanes of a quad, which the vector L1 serves together, and the 64
+// lanes of a load fall on few cache lines, and the mirrored second members
+// form the mirrored band.  Sorted pair k goes to thread k % 128, slot
+// k / 128; the 79 slots left over repeat the centre.  Entry: u & 0xff |
+// (v & 0xff) << 8.
 std::vector<uint16_t> gather_order()
 {
-    constexpr int kPositions = kWin * kWin, kThreads = 2 * 64;
+    constexpr int kThreads = 2 * 64, kSide = kWin + 1;
     std::vector<uint16_t> table((size_t)kGatherClasses * kThreads * kGatherThreadEntries, 0);
-    std::vector<int> idx(kPositions);
-    std::vector<double> row(kPositions), col(kPositions);
+    std::vector<std::pair<int, int>> units;
+    for (int v = 0; v <= kHalf; ++v)
+        for (int u = -kHalf; u <= kHalf; ++u)
+            if (v > 0 || u >= 0) units.emplace_back(u, v);        // (0, 0): the centre
+    const int n = (int)units.size();                             // (49^2 + 1) / 2 = 1201
+    std::vector<int> idx(n);
+    std::vector<double> row(n), col(n);
     for (int c = 0; c < kGatherClasses; ++c) {
         const double a = 2.0 * M_PI * (32.0 * c + 16.0) / kBins;
         const double cs = std::cos(a), sn = std::sin(a);
-        for (int p = 0; p < kPositions; ++p) {
-            const int u = p % kWin - kHalf, v = p / kWin - kHalf;
+        for (int p = 0; p < n; ++p) {
+            const int u = units[p].first, v = units[p].second;
             idx[p] = p;
             row[p] = std::floor(4.0 * (sn * u + cs * v));
             col[p] = cs * u - sn * v;
@@ -116,12 +127,14 @@ std::vector<uint16_t> gather_order()
             if (col[x] != col[y]) return col[x] < col[y];
             return x < y;
         });
-        for (int k = 0; k < kPositions; ++k) {
-            const int p = idx[k], u = p % kWin - kHalf, v = p / kWin - kHalf;
+        for (int k = 0; k < kThreads * kGatherPairs; ++k) {
+            const int p = k < n ? idx[k] : 0;                    // units[0] is the centre
+            const int u = units[p].first, v = units[p].second;
             table[((size_t)c * kThreads + k % kThreads) * kGatherThreadEntries + k / kThreads] =
                 (uint16_t)((u & 0xff) | ((v & 0xff) << 8));
         }
     }
+    static_assert(kSide * kSide / 2 + 1 <= kThreads * kGatherPairs, "pairs per thread");
     return table;
 }
 

@@ -60,19 +60,25 @@ int main()
     mix(c.data(), c.size() * 2);
     mix(s.data(), s.size() * 2);
 
-    // Gather order: every class lists each window position once.
+    // Gather order: in every class the pairs (u, v), (-u, -v) cover each
+    // position of [-24, 24]^2 once, except the centre, which pads the slots.
     const std::vector<uint16_t> order = gather_order();
     check(order.size() == (size_t)kGatherClasses * 128 * kGatherThreadEntries, "gather order size");
+    constexpr int kSide = kWin + 1;
     for (int cl = 0; cl < kGatherClasses; ++cl) {
-        std::vector<int> seen(kWin * kWin, 0);
+        std::vector<int> seen(kSide * kSide, 0);
         for (int t = 0; t < 128; ++t)
-            for (int m = 0; m < kWin * kWin / 128; ++m) {
+            for (int m = 0; m < kGatherPairs; ++m) {
                 const uint16_t e = order[((size_t)cl * 128 + t) * kGatherThreadEntries + m];
                 const int u = (int8_t)(e & 0xff), v = (int8_t)(e >> 8);
-                check(u >= -kHalf && u < kHalf && v >= -kHalf && v < kHalf, "gather entry range");
-                ++seen[(v + kHalf) * kWin + (u + kHalf)];
+                check(u >= -kHalf && u <= kHalf && v >= -kHalf && v <= kHalf, "gather entry range");
+                ++seen[(v + kHalf) * kSide + (u + kHalf)];
+                if (u || v) ++seen[(-v + kHalf) * kSide + (-u + kHalf)];
             }
-        for (int p = 0; p < kWin * kWin; ++p) check(seen[p] == 1, "gather order is a permutation");
+        const int centre = kHalf * kSide + kHalf;
+        for (int p = 0; p < kSide * kSide; ++p)
+            if (p != centre) check(seen[p] == 1, "gather pairs cover each position once");
+        check(seen[centre] == 128 * kGatherPairs - (kSide * kSide - 1) / 2, "centre pads the slots");
     }
     mix(order.data(), order.size() * 2);
 
