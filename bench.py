@@ -262,9 +262,9 @@ class Batch:
         self.plan.close()
 
 
-def roofline_of(kernels, desc_per_launch, pairs_per_launch, workload):
-    """Roofline object of the kernel with the largest time per step."""
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+def roofline_of(kernels, desc_per_launch, pairs_per_launch, workload, kernel=None):
+    """Roofline object of `kernel`, by default the kernel with the largest time per step."""
+    dom = kernel or max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
     sec = kd["avg_ms"] * 1e-3
     if dom in ("knn_batch_fp4", "knn_fp4"):
@@ -449,9 +449,21 @@ def main():
                             "knn_batch_popcount"))
     eager_wall, _ = timer.loop(sfm.run_eager, args.steps, 1)
     roof = roofline_of(kernels, total, n_pairs, "sfm")
+    # Every kernel of the step against its own roof; the extraction also
+    # against HBM, with the algorithmic bytes of a descriptor: its share of
+    # the images read once, its 16-byte keypoint and its 64-byte descriptor.
+    step_roofs = {k: roofline_of(kernels, total, n_pairs, "sfm", kernel=k)
+                  for k in kernels if k != "extract_order"}
+    if "extract" in kernels:
+        ex_bytes = sum(im.nbytes for im in imgs) + total * (16 + 64)
+        ex_sec = kernels["extract"]["avg_ms"] * 1e-3
+        step_roofs["extract"]["hbm"] = {
+            "algorithmic_bytes": ex_bytes, "achieved_gbs": ex_bytes / ex_sec / 1e9,
+            "frac": ex_bytes / ex_sec / 1e9 / PEAK_HBM_GBS}
     log("timed %d steps: %.3f ms per step" % (args.steps, ms_per_step))
 
     components = {"sfm_identical_to_plain_form": bool(identical), "sfm_error_flags": flags,
+                  "sfm_kernel_rooflines": step_roofs,
                   "sfm_eager_batched_ms_per_step": eager_wall / args.steps * 1e3}
     if "plain" in comps:
         p_wall, _ = timer.loop(plain_run, max(3, args.steps // 4), 1)
