@@ -399,7 +399,7 @@ def hd_component(torch, lat, timer, trip, steps, cpu_seconds):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
               "(requested --gpus %d)." % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:

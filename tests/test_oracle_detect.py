@@ -161,7 +161,7 @@ def test_orientation_bin_does_not_depend_on_last_bits_of_atan2():
     assert worst > 2 * err, (float(worst), err)
 
 
-# --- Suppression and border (the rule of the detector, fixed by this build:
+# --- Suppression and border (the rule of the detector, as the library fixes it:
 # keep a corner whose score is strictly above every corner among its 8
 # neighbours, and test only pixels at least 16 from every edge). ---
 

@@ -2,7 +2,7 @@
 
 The paper matches binary descriptors exhaustively under Hamming distance
 (Sec. 4, "Descriptor matching on the GPU") without stating k, the ratio test
-or ties; this build fixes k = 2, ties to the lowest train index and
+or ties; the library fixes k = 2, ties to the lowest train index and
 accept = d1 < ratio * d2 evaluated exactly.  Pinned against numpy bit
 unpacking, a full lexicographic sort, metric axioms and hand-built distances.
 """
