@@ -742,61 +742,86 @@ __global__ __launch_bounds__(256) void knn_popcount_kernel(SplitArgs a)
 
 // ---------------------------------------------------------------------------
 // Batched matching: many (query range, train range, output range) pairs in
-// one persistent launch.  Work item = (pair, 256-query group) over the pair's
+// one persistent launch.  Work item = (pair, query group) over the pair's
 // whole train range, so results are final and go straight to the outputs.
-// A one-block setup kernel validates the pairs, scans their item counts and
+// A one-block setup kernel validates the pairs, lays their items out and
 // resets the atomic work counter (so the sequence is replayable from a HIP
 // graph without memset nodes); a fill kernel writes the item -> pair map;
 // persistent workgroups then claim items through the counter.
+//
+// Items are laid out longest first (an item's time grows with its pair's
+// train rows): pairs go to 256 cost classes, 8 per doubling of the train
+// tile count, and the classes are laid out in decreasing order, so that the
+// last items claimed are the shortest and the workgroups finish together.
+// The order within a class follows the atomics and does not matter: every
+// item writes its own outputs.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ bool pair_ok(const PairEntry &e, int64_t query_rows, int64_t train_rows,
+                                        int64_t out_rows)
+{
+    return e.nq >= 0 && e.nt >= 0 && e.nq <= kMaxRows && e.nt <= kMaxSplitRows &&
+           e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
+           (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
+           e.out_first >= 0 && e.out_first + e.nq <= out_rows;
+}
+
+// Cost class of a pair, 0 for the longest items: 255 - floor(8 log2(tiles + 1))
+// with the fraction taken from the three bits after the leading one.
+__device__ __forceinline__ int cost_class(int64_t nt)
+{
+    nt = max((int64_t)0, min(nt, (int64_t)kMaxSplitRows));          // invalid pairs: any class
+    const uint32_t x = (uint32_t)((nt + kTileRows - 1) / kTileRows) + 1u;   // <= 2^16
+    const int lz = __clz((int)x);
+    const uint32_t frac = ((x << lz) >> 28) & 7u;
+    return 255 - min(255, 8 * (31 - lz) + (int)frac);
+}
+
 __global__ __launch_bounds__(256) void knn_batch_setup_kernel(
     const PairEntry *__restrict__ pairs, int n_pairs, int64_t query_rows, int64_t train_rows,
     int64_t out_rows, int64_t item_capacity, int group, PairInfo *__restrict__ info,
     BatchState *__restrict__ st, uint32_t *__restrict__ flags)
 {
-    __shared__ int64_t part[256];
+    __shared__ unsigned long long classes[256];
+    __shared__ int bad_s;
     const int tid = threadIdx.x;
-    const int chunk = (n_pairs + 255) / 256;
-    const int p0 = min(n_pairs, tid * chunk), p1 = min(n_pairs, p0 + chunk);
-    int64_t local = 0;
-    bool bad = false;
-    for (int p = p0; p < p1; ++p) {
-        const PairEntry e = pairs[p];
-        const bool ok = e.nq >= 0 && e.nt >= 0 && e.nq <= kMaxRows && e.nt <= kMaxSplitRows &&
-                        e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
-                        (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
-                        e.out_first >= 0 && e.out_first + e.nq <= out_rows;
-        bad |= !ok;
-        local += ok ? (e.nq + group - 1) / group : 0;
-    }
-    part[tid] = local;
+    classes[tid] = 0;
+    if (tid == 0) bad_s = 0;
     __syncthreads();
-    // Inclusive scan of the 256 chunk sums (Hillis-Steele).
+    // Items per class; each pair's rank in its class goes to info[p].item_first.
+    bool bad = false;
+    for (int p = tid; p < n_pairs; p += 256) {
+        const PairEntry e = pairs[p];
+        const bool ok = pair_ok(e, query_rows, train_rows, out_rows);
+        bad |= !ok;
+        const unsigned long long groups = ok ? (unsigned long long)((e.nq + group - 1) / group) : 0ull;
+        info[p].item_first = (int64_t)atomicAdd(&classes[cost_class(e.nt)], groups);
+    }
+    if (bad) atomicOr(&bad_s, 1);
+    __syncthreads();
+    // Inclusive scan of the 256 class totals (Hillis-Steele); class c's
+    // items start at the exclusive prefix.
     for (int off = 1; off < 256; off <<= 1) {
-        const int64_t v = tid >= off ? part[tid - off] : 0;
+        const unsigned long long v = tid >= off ? classes[tid - off] : 0ull;
         __syncthreads();
-        part[tid] += v;
+        classes[tid] += v;
         __syncthreads();
     }
+    const int64_t total = (int64_t)classes[255];
     // The item map holds item_capacity entries, enough for every batch whose
     // pairs' output ranges do not overlap; a batch that needs more is not run.
-    const bool overflow = part[255] > item_capacity;
-    int64_t first = part[tid] - local;
-    for (int p = p0; p < p1; ++p) {
+    const bool overflow = total > item_capacity;
+    for (int p = tid; p < n_pairs; p += 256) {
         const PairEntry e = pairs[p];
-        const bool ok = e.nq >= 0 && e.nt >= 0 && e.nq <= kMaxRows && e.nt <= kMaxSplitRows &&
-                        e.query_first >= 0 && e.query_first + e.nq <= query_rows &&
-                        (e.nt == 0 || (e.train_first >= 0 && e.train_first + e.nt <= train_rows)) &&
-                        e.out_first >= 0 && e.out_first + e.nq <= out_rows;
+        const bool ok = pair_ok(e, query_rows, train_rows, out_rows);
+        const int c = cost_class(e.nt);
         const int64_t groups = ok && !overflow ? (e.nq + group - 1) / group : 0;
-        info[p].item_first = first;
+        info[p].item_first += (int64_t)(c > 0 ? classes[c - 1] : 0ull);
         info[p].qgroups = (int32_t)groups;
         info[p].valid = ok && !overflow;
-        first += groups;
     }
-    if (bad || overflow) atomicOr(flags, kFlagBadPair);
+    if ((bad_s || overflow) && tid == 0) atomicOr(flags, kFlagBadPair);
     if (tid == 255) {
-        st->items = overflow ? 0 : part[255];
+        st->items = overflow ? 0 : total;
         st->next_item = 0;
     }
 }
