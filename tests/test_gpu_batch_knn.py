@@ -143,3 +143,47 @@ def test_long_train_ranges(torch_cuda, lat, path):
     rows, out_rows = consecutive_pairs(counts)
     check_pairs(torch_cuda, lat, D, rows, out_rows, 2, 0.8, path)
     assert lat.check_errors(clear=True) == 0
+
+
+@pytest.mark.parametrize("path", ["fp4", "mfma"])
+def test_many_pairs_across_cost_classes(torch_cuda, lat, path):
+    """700 pairs (more than the setup block's 256 threads) in random order,
+    train lengths log-uniform over 0..20,000 rows (work items laid out over
+    several dozen cost classes, longest first), query counts 0..300, train
+    ranges overlapping anywhere in the array: every pair's rows equal the
+    single hamming_knn call on its ranges, and a sample equals the oracle."""
+    from paper_1609_03986_amd.binding import pair_table
+    torch = torch_cuda
+    g = np.random.default_rng(21)
+    n_rows = 30_000
+    D = synth.random_descriptors(g, n_rows, 0.2)
+    n_pairs = 700
+    nt = np.floor(np.exp(g.uniform(0, np.log(20_001), n_pairs))).astype(np.int64) - 1
+    nt[g.choice(n_pairs, 20, replace=False)] = 0
+    nq = g.integers(0, 301, n_pairs)
+    rows, out = [], 0
+    for i in range(n_pairs):
+        qf = int(g.integers(0, n_rows - nq[i] + 1))
+        tf = int(g.integers(0, n_rows - nt[i] + 1))
+        rows.append((qf, int(nq[i]), tf, int(nt[i]), out))
+        out += int(nq[i])
+    Dd = dev(torch, D)
+    idx, dist, acc = lat.knn_batch(Dd, Dd, pair_table(rows), out, path=path)
+    torch.cuda.synchronize()
+    assert lat.check_errors(clear=True) == 0
+    idx, dist, acc = idx.cpu().numpy(), dist.cpu().numpy(), acc.cpu().numpy()
+    for i, (qf, q, tf, t, of) in enumerate(rows):
+        if q == 0:
+            continue
+        si, sd, sa = lat.knn(Dd[qf:qf + q], Dd[tf:tf + t], path=path)
+        torch.cuda.synchronize()
+        assert np.array_equal(idx[of:of + q], si.cpu().numpy()), (i, q, t)
+        assert np.array_equal(dist[of:of + q], sd.cpu().numpy()), (i, q, t)
+        assert np.array_equal(acc[of:of + q], sa.cpu().numpy()), (i, q, t)
+        if i % 7 == 0:
+            sel = np.arange(0, q, 37)
+            wi, wd, wa = oracle.knn(D[qf + sel], D[tf:tf + t])
+            assert np.array_equal(idx[of + sel], wi), (i, q, t)
+            assert np.array_equal(dist[of + sel], wd), (i, q, t)
+            assert np.array_equal(acc[of + sel], wa), (i, q, t)
+    assert lat.check_errors(clear=True) == 0
