@@ -738,8 +738,10 @@ def dense_component(torch, lat, timer, hd):
 
 def versions(torch):
     """ROCm, HIP runtime, driver and device names for the record."""
+    props = torch.cuda.get_device_properties(0)
     out = {"torch": torch.__version__, "hip": getattr(torch.version, "hip", None),
-           "device": torch.cuda.get_device_name(0)}
+           "device": torch.cuda.get_device_name(0),
+           "arch": getattr(props, "gcnArchName", None), "compute_units": props.multi_processor_count}
     try:
         out["rocm"] = open("/opt/rocm/.info/version").read().strip()
     except OSError:

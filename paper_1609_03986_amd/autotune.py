@@ -160,9 +160,14 @@ def tune(lat, buckets=None, reps=5, seed=0, log=None):
 
 
 def cache_key():
+    """Device architecture, compute-unit count and library version.  (Not the
+    marketing name: it comes from a libdrm table that an installation may
+    lack, and under rocprofv3 it reads as an empty string.)"""
     import torch
     from .binding import latch_version
-    return "%s|%s" % (torch.cuda.get_device_name(0), latch_version())
+    p = torch.cuda.get_device_properties(0)
+    arch = getattr(p, "gcnArchName", "").split(":")[0]
+    return "%s|%d CUs|%s" % (arch, p.multi_processor_count, latch_version())
 
 
 def load(lat, path=DEFAULT_CACHE):
