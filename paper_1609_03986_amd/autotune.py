@@ -4,8 +4,8 @@ path for batched matching, the MXFP4 tile shape (2 or 3 blocks of 32
 queries per wavefront), the split planner's workgroups-per-CU target and the
 persistent workgroups per CU of batched matching.  It measures the library's
 own kernels (HIP events recorded by the library on its launch stream) on
-random descriptors and caches the result per device kind (architecture and compute-unit count) and
-library version.
+random descriptors and caches the result per device kind (architecture and
+compute-unit count) and library version.
 
 Tuning never changes results (every path is exact), only speed.
 
