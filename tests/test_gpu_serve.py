@@ -58,8 +58,9 @@ def test_each_result_is_the_same_alone_and_in_the_mix(torch_cuda, triplets):
 def test_full_size_database_sampled(torch_cuda, triplets):
     """The serving configuration: a resident 1,000,000-row database extracted
     on the GPU from 50 seeded 1920x1080 images, requests from the uneven mix.
-    Database rows of the first image and 1,000 sampled queries (over three
-    requests, each against the whole database) equal the oracle."""
+    Every database row (the builder's images and keypoints regenerated from
+    its seed) and 1,000 sampled queries (over three requests, each against the
+    whole database) equal the oracle."""
     torch = torch_cuda
     from paper_1609_03986_amd.binding import Latch
     lat = Latch(triplets)
@@ -67,13 +68,13 @@ def test_full_size_database_sampled(torch_cuda, triplets):
         db = serve.build_database(lat)
         assert db.shape == (1_000_000, 16)
         db_np = db.cpu().numpy().view(np.uint32)
-        # The builder's first image and keypoints, regenerated from its seed.
+        # The builder's images and keypoints, regenerated from its seed.
         g = np.random.default_rng(3)
-        img0 = synth.smoothed_noise(g, 1080, 1920)
-        kps0 = synth.random_keypoints(g, 20000, 1080, 1920)
-        sel = np.arange(0, 20000, 97)
-        want, _ = oracle.extract(img0, kps0[sel], triplets)
-        assert np.array_equal(db_np[sel], want)
+        for i in range(50):
+            img = synth.smoothed_noise(g, 1080, 1920)
+            kps = synth.random_keypoints(g, 20000, 1080, 1920)
+            want, f = oracle.extract(img, kps, triplets)
+            assert f == 0 and np.array_equal(db_np[20000 * i:20000 * (i + 1)], want), i
         pool = serve.request_pool()
         reqs = serve.make_requests(3, 100.0, pool)
         ex = serve.GpuExecutor(db, triplets, n_slots=2)
