@@ -51,6 +51,7 @@ constexpr int kRoundsPerWave = 8 / kExtractWaves;         // 4
 constexpr int kGatherSlots = kGatherPairs;                // 10
 constexpr int kRawCentre = kRawBase + kHalf * kRawStride + kHalf;
 static_assert(kGatherSlots * kThreads >= ((kWin + 1) * (kWin + 1) + 1) / 2, "every pair once");
+static_assert(kGatherHeadPairs == 8 && kGatherSlots == 10, "one uint4 and one uint32 of entries");
 
 // Copy pass: units (row y, quadword q), 240 per window, unit e = 5 y + q.
 constexpr int kCopyUnits = kWin * kCopyQwords;
@@ -69,7 +70,7 @@ __device__ __forceinline__ uint32_t raw_of(uint32_t d, int h)
 }
 
 // Rule steps 4-5 for this thread's 10 position pairs of keypoint k: its
-// entries of the keypoint's angle class (two 16-byte loads; kept in e, two
+// entries of the keypoint's angle class (a 16-byte and a 4-byte load; kept in e, two
 // per dword, for write_raw), one pair of rounded offsets per position pair
 // (rounding half away from zero is odd: (-u, -v) samples at (-ox, -oy)), and
 // the byte loads of both members into g[2 m] and g[2 m + 1].
@@ -79,11 +80,10 @@ __device__ __forceinline__ void issue_gather(const Keypoint &k, const uint16_t *
                                              int tid, uint32_t (&e)[kGatherSlots / 2],
                                              uint32_t (&g)[2 * kGatherSlots])
 {
-    const uint4 *t = reinterpret_cast<const uint4 *>(
-        order + ((size_t)k.cls * kThreads + tid) * kGatherThreadEntries);
-    const uint4 t0 = t[0], t1 = t[1];
+    const uint16_t *cls = order + (size_t)k.cls * kGatherClassEntries;
+    const uint4 t0 = reinterpret_cast<const uint4 *>(cls)[tid];
     e[0] = t0.x, e[1] = t0.y, e[2] = t0.z, e[3] = t0.w;
-    e[4] = t1.x;
+    e[4] = reinterpret_cast<const uint32_t *>(cls + kGatherHeadPairs * kThreads)[tid];
     GlobalByte *img = (GlobalByte *)k.img;
     const int xm = k.width - 1, ym = k.height - 1;
 #pragma unroll

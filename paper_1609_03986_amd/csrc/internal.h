@@ -18,11 +18,14 @@ constexpr int kBins = 4096;
 // the band of a quarter image row at unit scale of the first, then by its
 // image column (host-built); for each of the 128 extraction threads its 10
 // pairs (entries 128 m + thread; the last slots repeat the centre) as 16-bit
-// entries u & 0xff | (v & 0xff) << 8, padded to 16 so that a thread reads
-// them with two 16-byte loads.
+// entries u & 0xff | (v & 0xff) << 8.  A class's table holds, for thread t,
+// pairs 0..7 at entries 8 t .. 8 t + 7 and pairs 8, 9 at entries
+// 1024 + 2 t, 1024 + 2 t + 1, so that a thread reads its pairs with one
+// 16-byte and one 4-byte load and every load of a wavefront is contiguous.
 constexpr int kGatherClasses = kBins / 32;
 constexpr int kGatherPairs = 10;
-constexpr int kGatherThreadEntries = 16;
+constexpr int kGatherHeadPairs = 8;
+constexpr int kGatherClassEntries = 128 * kGatherPairs;
 
 // Extraction LDS layout, per workgroup.
 //  * Copies s = 0..7: copy s holds, for every window row y and quadword
@@ -89,7 +92,7 @@ struct ExtractArgs {
     const int2 *rot;          // [4096] {cos_q14, sin_q14}
     const uint2 *trip_off;    // [512] by slot: {offA | off1 << 16, off2} LDS byte offsets
     const uint32_t *unperm;   // [128] per (wavefront, lane): slots of its four output bits
-    const uint16_t *gather;   // [kGatherClasses][128][kGatherThreadEntries] gather order
+    const uint16_t *gather;   // [kGatherClasses][kGatherClassEntries] gather order
     uint32_t *desc;
     uint32_t *flags;
     int num_cus;

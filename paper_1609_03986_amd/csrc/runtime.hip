@@ -22,7 +22,7 @@ struct latch_ctx {
     int2 *rot_dev = nullptr;           // [4096] {cos_q14, sin_q14}
     uint2 *trip_off_dev = nullptr;     // [512] by slot: LDS byte offsets of the three patches
     uint32_t *unperm_dev = nullptr;    // [128] output-bit slots per (wavefront, lane)
-    uint16_t *gather_dev = nullptr;    // [kGatherClasses][128][24] window gather order
+    uint16_t *gather_dev = nullptr;    // [kGatherClasses][kGatherClassEntries] window gather order
     uint32_t *flags_dev = nullptr;     // sticky error word
     // Weighted geometry (latch_create_geometry); window 0 runs the default kernel.
     int window = 0;
@@ -101,11 +101,12 @@ void rotation_table(int16_t *c, int16_t *s)
 // lanes of a load fall on few cache lines, and the mirrored second members
 // form the mirrored band.  Sorted pair k goes to thread k % 128, slot
 // k / 128; the 79 slots left over repeat the centre.  Entry: u & 0xff |
-// (v & 0xff) << 8.
+// (v & 0xff) << 8; slots 0..7 of thread t at 8 t + slot, slots 8 and 9 at
+// 1024 + 2 t + slot - 8 (one 16-byte and one 4-byte load per thread).
 std::vector<uint16_t> gather_order()
 {
     constexpr int kThreads = 2 * 64, kSide = kWin + 1;
-    std::vector<uint16_t> table((size_t)kGatherClasses * kThreads * kGatherThreadEntries, 0);
+    std::vector<uint16_t> table((size_t)kGatherClasses * kGatherClassEntries, 0);
     std::vector<std::pair<int, int>> units;
     for (int v = 0; v <= kHalf; ++v)
         for (int u = -kHalf; u <= kHalf; ++u)
@@ -130,8 +131,11 @@ std::vector<uint16_t> gather_order()
         for (int k = 0; k < kThreads * kGatherPairs; ++k) {
             const int p = k < n ? idx[k] : 0;                    // units[0] is the centre
             const int u = units[p].first, v = units[p].second;
-            table[((size_t)c * kThreads + k % kThreads) * kGatherThreadEntries + k / kThreads] =
-                (uint16_t)((u & 0xff) | ((v & 0xff) << 8));
+            const int t = k % kThreads, m = k / kThreads;
+            const int at = m < kGatherHeadPairs ? kGatherHeadPairs * t + m
+                                                : kGatherHeadPairs * kThreads +
+                                                      (kGatherPairs - kGatherHeadPairs) * t + m - kGatherHeadPairs;
+            table[(size_t)c * kGatherClassEntries + at] = (uint16_t)((u & 0xff) | ((v & 0xff) << 8));
         }
     }
     static_assert(kSide * kSide / 2 + 1 <= kThreads * kGatherPairs, "pairs per thread");

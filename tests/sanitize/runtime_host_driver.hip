@@ -63,13 +63,17 @@ int main()
     // Gather order: in every class the pairs (u, v), (-u, -v) cover each
     // position of [-24, 24]^2 once, except the centre, which pads the slots.
     const std::vector<uint16_t> order = gather_order();
-    check(order.size() == (size_t)kGatherClasses * 128 * kGatherThreadEntries, "gather order size");
+    check(order.size() == (size_t)kGatherClasses * kGatherClassEntries, "gather order size");
     constexpr int kSide = kWin + 1;
     for (int cl = 0; cl < kGatherClasses; ++cl) {
         std::vector<int> seen(kSide * kSide, 0);
         for (int t = 0; t < 128; ++t)
             for (int m = 0; m < kGatherPairs; ++m) {
-                const uint16_t e = order[((size_t)cl * 128 + t) * kGatherThreadEntries + m];
+                const size_t at = m < kGatherHeadPairs ? (size_t)kGatherHeadPairs * t + m
+                                                       : (size_t)kGatherHeadPairs * 128 +
+                                                             (size_t)(kGatherPairs - kGatherHeadPairs) * t +
+                                                             (m - kGatherHeadPairs);
+                const uint16_t e = order[(size_t)cl * kGatherClassEntries + at];
                 const int u = (int8_t)(e & 0xff), v = (int8_t)(e >> 8);
                 check(u >= -kHalf && u <= kHalf && v >= -kHalf && v <= kHalf, "gather entry range");
                 ++seen[(v + kHalf) * kSide + (u + kHalf)];
