@@ -5,15 +5,15 @@
 //   1. resampling rule steps 1-3 on the keypoint (uniform across the group);
 //   2. gather of the 48 x 48 upright window (steps 4-5), one byte load per
 //      window position.  Rounding half away from zero is odd, so positions
-//      (u, v) and (-u, -v) sample at offsets (ox, oy) and (-ox, -oy): a thread
-//      rounds once for each of its 10 position pairs (over [-24, 24]^2; the
-//      extra row and column are gathered and not read).  The vector L1 serves
-//      a load one cache line at a time, so the pairs are taken in an order
-//      that keeps each load's 64 samples on few lines: for the keypoint's
-//      angle class (32 bins), sorted by the band of image rows their first
-//      member samples at the class's middle angle, then by column (a
-//      host-built table).  A load then covers a band about s image rows high
-//      (s the scale), its mirrored loads the mirrored band.  The loads are
+//      (u, v) and (-u, -v) sample at offsets (ox, oy) and (-ox, -oy), and the
+//      unrounded offsets of (u + 1, v) are those of (u, v) plus a per-keypoint
+//      constant: a thread takes 5 chains (u, v), (u + 1, v), (-u, -v),
+//      (-u - 1, -v) with two roundings per coordinate each (over
+//      [-24, 24]^2; the extra row and column are gathered and not read).
+//      The chains are taken in an order that keeps each load's samples on
+//      nearby image bytes: for the keypoint's angle class (32 bins), sorted
+//      by the band of image rows their first member samples at the class's
+//      middle angle, then by column (a host-built table).  The loads are
 //      issued one keypoint ahead so that their latency overlaps the previous
 //      descriptor's arithmetic;
 //   3. the samples are written to a plain window in LDS, and a copy pass
@@ -46,12 +46,12 @@ namespace {
 constexpr int kThreads = kExtractWaves * 64;             // 128: two wavefronts per window
 constexpr int kRoundsPerWave = 8 / kExtractWaves;         // 4
 
-// Gather slots per thread: position pairs 128 m + tid of the gather order,
-// two samples each.
-constexpr int kGatherSlots = kGatherPairs;                // 10
+// Gather slots per thread: chains 128 m + tid of the gather order, four
+// samples each.
+constexpr int kGatherSlots = kGatherChains;               // 5
 constexpr int kRawCentre = kRawBase + kHalf * kRawStride + kHalf;
-static_assert(kGatherSlots * kThreads >= ((kWin + 1) * (kWin + 1) + 1) / 2, "every pair once");
-static_assert(kGatherHeadPairs == 8 && kGatherSlots == 10, "one uint4 and one uint32 of entries");
+static_assert(kGatherHeadChains == 4 && kGatherSlots == 5, "one uint2 and one uint16 of entries");
+static_assert(kRawStride >= kWin + 1, "raw rows hold u = -24 .. 24");
 
 // Copy pass: units (row y, quadword q), 240 per window, unit e = 5 y + q.
 constexpr int kCopyUnits = kWin * kCopyQwords;
@@ -60,8 +60,9 @@ static_assert(kWinLdsBytes * 8 <= kLdsPerCu, "eight windows per CU");
 
 #include "keypoint.h"
 
-// Raw-window byte of the position in half `h` of packed entry pair `d` (the
-// first member of its pair; the second is at 2 kRawCentre minus it).
+// Raw-window byte of the first member (u, v) of the chain in half `h` of
+// packed entry pair `d`; (u + 1, v) is the next byte, (-u, -v) sits at
+// 2 kRawCentre minus it and (-u - 1, -v) one byte before that.
 __device__ __forceinline__ uint32_t raw_of(uint32_t d, int h)
 {
     const int u = __builtin_amdgcn_sbfe((int)d, 16 * h, 8);
@@ -69,54 +70,70 @@ __device__ __forceinline__ uint32_t raw_of(uint32_t d, int h)
     return (uint32_t)(kRawCentre + mad_i24(v, kRawStride, u));
 }
 
-// Rule steps 4-5 for this thread's 10 position pairs of keypoint k: its
-// entries of the keypoint's angle class (a 16-byte and a 4-byte load; kept in e, two
-// per dword, for write_raw), one pair of rounded offsets per position pair
-// (rounding half away from zero is odd: (-u, -v) samples at (-ox, -oy)), and
-// the byte loads of both members into g[2 m] and g[2 m + 1].
-// sq (C u - S v) is formed from 24-bit products: |C u - S v| < 2^20 and
-// sq <= 2^10, so every product is exact and full rate.
+// Rule steps 4-5 for this thread's 5 chains of keypoint k: its entries of
+// the keypoint's angle class (an 8-byte and a 2-byte load; kept in e, two per
+// dword, for write_raw) and the byte loads of chain m's members (u, v),
+// (u + 1, v), (-u, -v), (-u - 1, -v) into g[4 m .. 4 m + 3].  The unrounded
+// offsets of (u, v) are sq (C u - S v) and sq (S u + C v), formed from
+// 24-bit products (|C u - S v| < 2^20 and sq <= 2^10, so every product is
+// exact and full rate); those of (u + 1, v) add sq C and sq S (|sq C| <= 2^24,
+// a scalar product), and rounding half away from zero is odd, so the mirrors
+// sample at the negated offsets.  Two roundings per coordinate serve the
+// chain's four samples.
 __device__ __forceinline__ void issue_gather(const Keypoint &k, const uint16_t *__restrict__ order,
-                                             int tid, uint32_t (&e)[kGatherSlots / 2],
-                                             uint32_t (&g)[2 * kGatherSlots])
+                                             int tid, uint32_t (&e)[(kGatherSlots + 1) / 2],
+                                             uint32_t (&g)[4 * kGatherSlots])
 {
     const uint16_t *cls = order + (size_t)k.cls * kGatherClassEntries;
-    const uint4 t0 = reinterpret_cast<const uint4 *>(cls)[tid];
-    e[0] = t0.x, e[1] = t0.y, e[2] = t0.z, e[3] = t0.w;
-    e[4] = reinterpret_cast<const uint32_t *>(cls + kGatherHeadPairs * kThreads)[tid];
+    const uint2 t0 = reinterpret_cast<const uint2 *>(cls)[tid];
+    e[0] = t0.x, e[1] = t0.y;
+    e[2] = cls[kGatherHeadChains * kThreads + tid];
     GlobalByte *img = (GlobalByte *)k.img;
     const int xm = k.width - 1, ym = k.height - 1;
+    const int sqc = k.sq * k.c, sqs = k.sq * k.s;
 #pragma unroll
     for (int m = 0; m < kGatherSlots; ++m) {
         const int u = __builtin_amdgcn_sbfe((int)e[m >> 1], 16 * (m & 1), 8);
         const int v = __builtin_amdgcn_sbfe((int)e[m >> 1], 16 * (m & 1) + 8, 8);
-        const int ox = round_q22(mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))));
-        const int oy = round_q22(mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
-        uint32_t a0, a1;
+        const int nx = mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v)));
+        const int ny = mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v)));
+        const int ox0 = round_q22(nx), oy0 = round_q22(ny);
+        const int ox1 = round_q22(nx + sqc), oy1 = round_q22(ny + sqs);
+        uint32_t a[4];
         if (k.interior) {
             // Every sample is inside the image, so |offset| * pitch < 2^31 and the
-            // 24-bit multiply-add is exact.
-            const int d = mad_i24_s(k.pitch, oy, ox);
-            a0 = (uint32_t)(k.centre + d);
-            a1 = (uint32_t)(k.centre - d);
+            // 24-bit multiply-adds are exact.
+            const int d0 = mad_i24_s(k.pitch, oy0, ox0);
+            const int d1 = mad_i24_s(k.pitch, oy1, ox1);
+            a[0] = (uint32_t)(k.centre + d0);
+            a[1] = (uint32_t)(k.centre + d1);
+            a[2] = (uint32_t)(k.centre - d0);
+            a[3] = (uint32_t)(k.centre - d1);
         } else {
-            a0 = (uint32_t)mad_i24(clamp_med3(k.cy + oy, 0, ym), k.pitch, clamp_med3(k.cx + ox, 0, xm));
-            a1 = (uint32_t)mad_i24(clamp_med3(k.cy - oy, 0, ym), k.pitch, clamp_med3(k.cx - ox, 0, xm));
+            a[0] = (uint32_t)mad_i24(clamp_med3(k.cy + oy0, 0, ym), k.pitch, clamp_med3(k.cx + ox0, 0, xm));
+            a[1] = (uint32_t)mad_i24(clamp_med3(k.cy + oy1, 0, ym), k.pitch, clamp_med3(k.cx + ox1, 0, xm));
+            a[2] = (uint32_t)mad_i24(clamp_med3(k.cy - oy0, 0, ym), k.pitch, clamp_med3(k.cx - ox0, 0, xm));
+            a[3] = (uint32_t)mad_i24(clamp_med3(k.cy - oy1, 0, ym), k.pitch, clamp_med3(k.cx - ox1, 0, xm));
         }
-        g[2 * m] = img[a0];
-        g[2 * m + 1] = img[a1];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) g[4 * m + i] = img[a[i]];
     }
 }
 
-// The gathered samples into the raw window.
-__device__ __forceinline__ void write_raw(uint8_t *lds, const uint32_t (&e)[kGatherSlots / 2],
-                                          const uint32_t (&g)[2 * kGatherSlots])
+// The gathered samples into the raw window.  Chains overlap at the end of a
+// row and the padding slots repeat the centre's chain: such bytes are written
+// more than once, always with the same sample.
+__device__ __forceinline__ void write_raw(uint8_t *lds, const uint32_t (&e)[(kGatherSlots + 1) / 2],
+                                          const uint32_t (&g)[4 * kGatherSlots])
 {
 #pragma unroll
     for (int m = 0; m < kGatherSlots; ++m) {
         const uint32_t r = raw_of(e[m >> 1], m & 1);
-        lds[r] = (uint8_t)g[2 * m];
-        lds[2 * kRawCentre - r] = (uint8_t)g[2 * m + 1];
+        const uint32_t rm = 2 * kRawCentre - 1 - r;          // (-u - 1, -v)
+        lds[r] = (uint8_t)g[4 * m];
+        lds[r + 1] = (uint8_t)g[4 * m + 1];
+        lds[rm + 1] = (uint8_t)g[4 * m + 2];
+        lds[rm] = (uint8_t)g[4 * m + 3];
     }
 }
 
@@ -273,7 +290,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4, 4))
     // (slots >> 8 k) & 0xff of its wavefront (constant over keypoints).
     const uint32_t slots = unperm[64 * wave + lane];
     const int64_t stride = range.stride;
-    uint32_t e[kGatherSlots / 2], g[2 * kGatherSlots];
+    uint32_t e[(kGatherSlots + 1) / 2], g[4 * kGatherSlots];
     KeypointBatch batch = prepare_batch<kTable, kHalf>(kps, n, p, stride, lane, rot, src);
     bool bad_image = false;
     Keypoint cur = batch_get<kTable>(batch, 0, src, &bad_image);

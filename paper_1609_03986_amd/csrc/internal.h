@@ -13,19 +13,21 @@ constexpr int kPatchR = 3;               // 7 x 7 patches
 constexpr int kTriplets = 512;
 constexpr int kWords = 16;
 constexpr int kBins = 4096;
-// Window gather order: per angle class (32 bins), pairs of window positions
-// (u, v), (-u, -v) over [-24, 24]^2 (1,200 pairs and the centre), sorted by
-// the band of a quarter image row at unit scale of the first, then by its
-// image column (host-built); for each of the 128 extraction threads its 10
-// pairs (entries 128 m + thread; the last slots repeat the centre) as 16-bit
-// entries u & 0xff | (v & 0xff) << 8.  A class's table holds, for thread t,
-// pairs 0..7 at entries 8 t .. 8 t + 7 and pairs 8, 9 at entries
-// 1024 + 2 t, 1024 + 2 t + 1, so that a thread reads its pairs with one
-// 16-byte and one 4-byte load and every load of a wavefront is contiguous.
+// Window gather order: per angle class (32 bins), chains of four window
+// positions (u, v), (u + 1, v) and their mirrors (-u, -v), (-u - 1, -v),
+// covering [-24, 24]^2 (613 chains; the first members of a row's chains
+// overlap by one position at its end), sorted by the band of a quarter image
+// row at unit scale of the first member, then by its image column
+// (host-built); for each of the 128 extraction threads its 5 chains (chains
+// 128 m + thread; the last slots repeat the centre's chain) as 16-bit entries
+// u & 0xff | (v & 0xff) << 8.  A class's table holds, for thread t, chains
+// 0..3 at entries 4 t .. 4 t + 3 and chain 4 at entry 512 + t, so that a
+// thread reads its chains with one 8-byte and one 2-byte load and every load
+// of a wavefront is contiguous.
 constexpr int kGatherClasses = kBins / 32;
-constexpr int kGatherPairs = 10;
-constexpr int kGatherHeadPairs = 8;
-constexpr int kGatherClassEntries = 128 * kGatherPairs;
+constexpr int kGatherChains = 5;
+constexpr int kGatherHeadChains = 4;
+constexpr int kGatherClassEntries = 128 * kGatherChains;
 
 // Extraction LDS layout, per workgroup.
 //  * Copies s = 0..7: copy s holds, for every window row y and quadword

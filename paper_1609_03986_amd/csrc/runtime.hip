@@ -89,29 +89,34 @@ void rotation_table(int16_t *c, int16_t *s)
 
 // Gather order of the extraction kernel.  Rounding half away from zero is
 // odd, so positions (u, v) and (-u, -v) sample at offsets (ox, oy) and
-// (-ox, -oy): the kernel rounds once per pair.  Over [-24, 24]^2 (the
-// window and one more row and column, which nothing reads) that is 1,200
-// pairs, taken with first member (u, v) with v > 0, or v = 0 and u > 0, plus
-// the centre.  For angle class c (bins 32 c .. 32 c + 31), with (C, S) the
-// cosine and sine of the class's middle angle, position (u, v) samples image
-// row offset about s (S u + C v) and column offset s (C u - S v) at scale s.
-// Pairs are sorted by the band floor(4 (S u + C v)) of their first member (a
-// quarter row at unit scale), then by its column offset (ties by position):
-// the four lanes of a quad, which the vector L1 serves together, and the 64
-// lanes of a load fall on few cache lines, and the mirrored second members
-// form the mirrored band.  Sorted pair k goes to thread k % 128, slot
-// k / 128; the 79 slots left over repeat the centre.  Entry: u & 0xff |
-// (v & 0xff) << 8; slots 0..7 of thread t at 8 t + slot, slots 8 and 9 at
-// 1024 + 2 t + slot - 8 (one 16-byte and one 4-byte load per thread).
+// (-ox, -oy), and the unrounded offsets of (u + 1, v) are those of (u, v)
+// plus s C and s S: the kernel takes positions in chains (u, v), (u + 1, v),
+// (-u, -v), (-u - 1, -v), with two rounded offset pairs per chain.  Over
+// [-24, 24]^2 (the window and one more row and column, which nothing reads)
+// the first members run over rows v = 1..24 with u = -24, -22, .., 22 and 23
+// (the last chain overlaps the one before it at (23, v)), and over row 0
+// with u = 0, 2, .., 22 and 23: 613 chains, whose mirrors cover the other
+// half.  For angle class c (bins 32 c .. 32 c + 31), with (C, S) the cosine
+// and sine of the class's middle angle, position (u, v) samples image row
+// offset about s (S u + C v) and column offset s (C u - S v) at scale s.
+// Chains are sorted by the band floor(4 (S u + C v)) of their first member
+// (a quarter row at unit scale), then by its column offset (ties by
+// position), so that the lanes of a load sample nearby image bytes and the
+// mirrored members form the mirrored band.  Sorted chain k goes to thread
+// k % 128, slot k / 128; the 27 slots left over repeat the centre's chain
+// (0, 0), (1, 0).  Entry: u & 0xff | (v & 0xff) << 8; slots 0..3 of thread t
+// at 4 t + slot, slot 4 at 512 + t (one 8-byte and one 2-byte load per
+// thread).
 std::vector<uint16_t> gather_order()
 {
-    constexpr int kThreads = 2 * 64, kSide = kWin + 1;
+    constexpr int kThreads = 2 * 64;
     std::vector<uint16_t> table((size_t)kGatherClasses * kGatherClassEntries, 0);
-    std::vector<std::pair<int, int>> units;
-    for (int v = 0; v <= kHalf; ++v)
-        for (int u = -kHalf; u <= kHalf; ++u)
-            if (v > 0 || u >= 0) units.emplace_back(u, v);        // (0, 0): the centre
-    const int n = (int)units.size();                             // (49^2 + 1) / 2 = 1201
+    std::vector<std::pair<int, int>> units;                      // first members
+    for (int v = 0; v <= kHalf; ++v) {
+        for (int u = v > 0 ? -kHalf : 0; u < kHalf - 1; u += 2) units.emplace_back(u, v);
+        units.emplace_back(kHalf - 1, v);                        // (23, v), (24, v)
+    }
+    const int n = (int)units.size();                             // 24 * 25 + 13 = 613
     std::vector<int> idx(n);
     std::vector<double> row(n), col(n);
     for (int c = 0; c < kGatherClasses; ++c) {
@@ -128,17 +133,17 @@ std::vector<uint16_t> gather_order()
             if (col[x] != col[y]) return col[x] < col[y];
             return x < y;
         });
-        for (int k = 0; k < kThreads * kGatherPairs; ++k) {
-            const int p = k < n ? idx[k] : 0;                    // units[0] is the centre
+        for (int k = 0; k < kThreads * kGatherChains; ++k) {
+            const int p = k < n ? idx[k] : 0;                    // units[0]: the centre's chain
             const int u = units[p].first, v = units[p].second;
             const int t = k % kThreads, m = k / kThreads;
-            const int at = m < kGatherHeadPairs ? kGatherHeadPairs * t + m
-                                                : kGatherHeadPairs * kThreads +
-                                                      (kGatherPairs - kGatherHeadPairs) * t + m - kGatherHeadPairs;
+            const int at = m < kGatherHeadChains ? kGatherHeadChains * t + m
+                                                 : kGatherHeadChains * kThreads + t;
             table[(size_t)c * kGatherClassEntries + at] = (uint16_t)((u & 0xff) | ((v & 0xff) << 8));
         }
     }
-    static_assert(kSide * kSide / 2 + 1 <= kThreads * kGatherPairs, "pairs per thread");
+    static_assert(24 * 25 + 13 <= kThreads * kGatherChains, "chains per thread");
+    static_assert(kGatherChains == kGatherHeadChains + 1, "one chain after the head");
     return table;
 }
 

@@ -60,29 +60,31 @@ int main()
     mix(c.data(), c.size() * 2);
     mix(s.data(), s.size() * 2);
 
-    // Gather order: in every class the pairs (u, v), (-u, -v) cover each
-    // position of [-24, 24]^2 once, except the centre, which pads the slots.
+    // Gather order: in every class the chains (u, v), (u + 1, v), (-u, -v),
+    // (-u - 1, -v) cover every position of [-24, 24]^2, stay inside it, and
+    // the 27 padding slots repeat the centre's chain.
     const std::vector<uint16_t> order = gather_order();
     check(order.size() == (size_t)kGatherClasses * kGatherClassEntries, "gather order size");
     constexpr int kSide = kWin + 1;
     for (int cl = 0; cl < kGatherClasses; ++cl) {
         std::vector<int> seen(kSide * kSide, 0);
+        int centre_chains = 0;
         for (int t = 0; t < 128; ++t)
-            for (int m = 0; m < kGatherPairs; ++m) {
-                const size_t at = m < kGatherHeadPairs ? (size_t)kGatherHeadPairs * t + m
-                                                       : (size_t)kGatherHeadPairs * 128 +
-                                                             (size_t)(kGatherPairs - kGatherHeadPairs) * t +
-                                                             (m - kGatherHeadPairs);
+            for (int m = 0; m < kGatherChains; ++m) {
+                const size_t at = m < kGatherHeadChains ? (size_t)kGatherHeadChains * t + m
+                                                        : (size_t)kGatherHeadChains * 128 + t;
                 const uint16_t e = order[(size_t)cl * kGatherClassEntries + at];
                 const int u = (int8_t)(e & 0xff), v = (int8_t)(e >> 8);
-                check(u >= -kHalf && u <= kHalf && v >= -kHalf && v <= kHalf, "gather entry range");
-                ++seen[(v + kHalf) * kSide + (u + kHalf)];
-                if (u || v) ++seen[(-v + kHalf) * kSide + (-u + kHalf)];
+                check(u >= -kHalf && u + 1 <= kHalf && v >= 0 && v <= kHalf && (v > 0 || u >= 0),
+                      "gather chain range");
+                centre_chains += u == 0 && v == 0;
+                for (int d = 0; d < 2; ++d) {
+                    ++seen[(v + kHalf) * kSide + (u + d + kHalf)];
+                    ++seen[(-v + kHalf) * kSide + (-u - d + kHalf)];
+                }
             }
-        const int centre = kHalf * kSide + kHalf;
-        for (int p = 0; p < kSide * kSide; ++p)
-            if (p != centre) check(seen[p] == 1, "gather pairs cover each position once");
-        check(seen[centre] == 128 * kGatherPairs - (kSide * kSide - 1) / 2, "centre pads the slots");
+        for (int p = 0; p < kSide * kSide; ++p) check(seen[p] >= 1, "gather chains cover each position");
+        check(centre_chains == 128 * kGatherChains - (24 * 25 + 13) + 1, "centre chain pads the slots");
     }
     mix(order.data(), order.size() * 2);
 
