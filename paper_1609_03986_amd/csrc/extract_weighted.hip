@@ -3,12 +3,15 @@
 // patch pixel; zero weights on one row and one column give the 7 x 7 patch).
 //
 // For each triplet, S_j = sum w[a][b] (A[a][b] - P_j[a][b])^2 over the patch
-// pixels and bit = [S_1 > S_2].  Weights lie in [0, 128], so w d fits a signed
-// 16-bit lane for every pixel difference d in [-255, 255]: per patch row of 8
-// pixels (4 pairs) the kernel forms d with v_pk_sub_i16, w d with
-// v_pk_mul_lo_u16 and accumulates d (w d) with v_dot2_i32_i16.  Every sum is
-// below 64 * 128 * 255^2 < 2^31: exact.  7 x 7 patches run as 8 x 8 ones
-// whose last row and column weigh 0.
+// pixels and bit = [S_1 > S_2].  Per pixel,
+//     w (A - P_1)^2 - w (A - P_2)^2 = w d s,  d = P_1 - P_2,  s = P_1 + P_2 - 2 A,
+// so bit = [sum w d s > 0].  Weights lie in [0, 128], d in [-255, 255] and s in
+// [-510, 510], so d, s and w d fit signed 16-bit lanes: per patch row of 8
+// pixels (4 pairs) the kernel forms d, P_1 + P_2 and s with packed 16-bit
+// subtract, add and multiply-add, w d with a packed 16-bit multiply, and
+// accumulates (w d) s with v_dot2_i32_i16.  |sum| <= 64 * 128 * 255 * 510
+// < 2^31: exact.  7 x 7 patches run as 8 x 8 ones whose last row and column
+// weigh 0.
 //
 // A workgroup of four wavefronts computes one descriptor at a time
 // (grid-stride over keypoints):
@@ -43,26 +46,45 @@ struct WGeom {
     static_assert(kW * kW % kWThreads == 0, "whole samples per thread");
 };
 
-// Rule steps 4-5 for window position q = i W + j (u = j - W/2, v = i - W/2).
-template <int kW>
-__device__ __forceinline__ uint32_t sample(const Keypoint &k, GlobalByte *img, int q)
+// Rule steps 4-5 for the sample of unrounded offsets (nx, ny) = (sq (C u - S v),
+// sq (S u + C v)) of a window position (u, v).
+__device__ __forceinline__ uint32_t sample_at(const Keypoint &k, GlobalByte *img, int nx, int ny)
 {
-    const int u = (q % kW) - WGeom<kW>::kHalfW, v = (q / kW) - WGeom<kW>::kHalfW;
-    const int ox = round_q22(mul_i24(mad_i24(k.c, u, mul_i24(-k.s, v)), k.sq));
-    const int oy = round_q22(mul_i24(mad_i24(k.s, u, mul_i24(k.c, v)), k.sq));
-    if (k.interior) return img[(uint32_t)(k.cy * k.pitch + k.cx + mad_i24(oy, k.pitch, ox))];
+    const int ox = round_q22(nx), oy = round_q22(ny);
+    if (k.interior) return img[(uint32_t)(k.centre + mad_i24_s(k.pitch, oy, ox))];
     const int x = clamp_med3(k.cx + ox, 0, k.width - 1);
     const int y = clamp_med3(k.cy + oy, 0, k.height - 1);
     return img[(uint32_t)mad_i24(y, k.pitch, x)];
 }
 
+// This thread's samples: window positions q = tid + 256 m (u = q mod W - W/2,
+// v = q div W - W/2).  |C u - S v| < 2^20 and sq <= 2^10, so the 24-bit
+// products are exact.  When W divides 256 every sample of a thread has the
+// same u and v grows by 256 / W per sample, so the unrounded offsets step by
+// the keypoint's -(256 / W) sq S and (256 / W) sq C (|step| <= 2^26, exact).
 template <int kW>
 __device__ __forceinline__ void issue_samples(const Keypoint &k, int tid,
                                               uint32_t (&g)[WGeom<kW>::kSamples])
 {
+    using G = WGeom<kW>;
     GlobalByte *img = (GlobalByte *)k.img;
+    if constexpr (kWThreads % kW == 0) {
+        constexpr int kDv = kWThreads / kW;
+        const int u = tid % kW - G::kHalfW, v = tid / kW - G::kHalfW;
+        int nx = mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v)));
+        int ny = mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v)));
+        const int dx = -kDv * k.sq * k.s, dy = kDv * k.sq * k.c;
 #pragma unroll
-    for (int m = 0; m < WGeom<kW>::kSamples; ++m) g[m] = sample<kW>(k, img, tid + kWThreads * m);
+        for (int m = 0; m < G::kSamples; ++m, nx += dx, ny += dy) g[m] = sample_at(k, img, nx, ny);
+    } else {
+#pragma unroll
+        for (int m = 0; m < G::kSamples; ++m) {
+            const int q = tid + kWThreads * m;
+            const int u = q % kW - G::kHalfW, v = q / kW - G::kHalfW;
+            g[m] = sample_at(k, img, mul_i24_s(k.sq, mad_i24_s(k.c, u, mul_i24_s(-k.s, v))),
+                             mul_i24_s(k.sq, mad_i24_s(k.s, u, mul_i24_s(k.c, v))));
+        }
+    }
 }
 
 // Pixel (i, j) goes to element j - s of row i of copy s, s = 0..3 (j >= s).
@@ -113,32 +135,45 @@ __device__ __forceinline__ void load_row_pair(uint32_t pa, uint32_t pc, uint32_t
         : "memory");
 }
 
-// One patch row (4 pixel pairs) of S_1 and S_2.
+// c + a b per 16-bit half (v_pk_mad_i16; the compiler splits the multiply-add
+// of 16-bit vectors into a shift, an add and a subtract).  b is uniform.
+__device__ __forceinline__ short2v pk_mad_i16(short2v a, uint32_t b, short2v c)
+{
+    uint32_t r;
+    asm("v_pk_mad_i16 %0, %1, %2, %3"
+        : "=v"(r)
+        : "v"(__builtin_bit_cast(uint32_t, a)), "s"(b), "v"(__builtin_bit_cast(uint32_t, c)));
+    return __builtin_bit_cast(short2v, r);
+}
+
+// One patch row (4 pixel pairs) of sum w d s.
 __device__ __forceinline__ void weighted_row(const uint32_t *wrow, uint64_t a0, uint64_t a1, uint64_t c0,
-                                             uint64_t c1, uint64_t e0, uint64_t e1, int &s1, int &s2)
+                                             uint64_t c1, uint64_t e0, uint64_t e1, int &acc)
 {
     const uint32_t av[4] = {(uint32_t)a0, (uint32_t)(a0 >> 32), (uint32_t)a1, (uint32_t)(a1 >> 32)};
     const uint32_t cv[4] = {(uint32_t)c0, (uint32_t)(c0 >> 32), (uint32_t)c1, (uint32_t)(c1 >> 32)};
     const uint32_t ev[4] = {(uint32_t)e0, (uint32_t)(e0 >> 32), (uint32_t)e1, (uint32_t)(e1 >> 32)};
+    constexpr uint32_t kMinus2 = 0xfffefffeu;       // -2 in both 16-bit halves
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const short2v wv = __builtin_bit_cast(short2v, wrow[i]);
         const short2v A = __builtin_bit_cast(short2v, av[i]);
-        const short2v d1 = A - __builtin_bit_cast(short2v, cv[i]);
-        const short2v d2 = A - __builtin_bit_cast(short2v, ev[i]);
-        s1 = __builtin_amdgcn_sdot2(wv * d1, d1, s1, false);
-        s2 = __builtin_amdgcn_sdot2(wv * d2, d2, s2, false);
+        const short2v P1 = __builtin_bit_cast(short2v, cv[i]);
+        const short2v P2 = __builtin_bit_cast(short2v, ev[i]);
+        const short2v d = P1 - P2;
+        const short2v s = pk_mad_i16(A, kMinus2, P1 + P2);
+        acc = __builtin_amdgcn_sdot2(wv * d, s, acc, false);
     }
 }
 
 template <int kR, int kRowBytes>
 __device__ __forceinline__ void weighted_rows(uint32_t base, uint32_t oa, uint32_t o1, uint32_t o2,
-                                              const WeightRows &w, int &s1, int &s2)
+                                              const WeightRows &w, int &acc)
 {
     uint64_t v[12];
     load_row_pair<kR * kRowBytes, kRowBytes>(base + oa, base + o1, base + o2, v);
-    weighted_row(w.pair + 4 * kR, v[0], v[1], v[2], v[3], v[4], v[5], s1, s2);
-    weighted_row(w.pair + 4 * (kR + 1), v[6], v[7], v[8], v[9], v[10], v[11], s1, s2);
+    weighted_row(w.pair + 4 * kR, v[0], v[1], v[2], v[3], v[4], v[5], acc);
+    weighted_row(w.pair + 4 * (kR + 1), v[6], v[7], v[8], v[9], v[10], v[11], acc);
 }
 
 // S_j of one triplet: patch rows at byte offsets off + r kRowBytes.
@@ -148,12 +183,12 @@ __device__ __forceinline__ bool weighted_bit(const uint8_t *lds, uint32_t oa, ui
 {
     constexpr int kRB = WGeom<kW>::kRowBytes;
     const uint32_t base = (uint32_t)(uintptr_t)lds;
-    int s1 = 0, s2 = 0;
-    weighted_rows<0, kRB>(base, oa, o1, o2, w, s1, s2);
-    weighted_rows<2, kRB>(base, oa, o1, o2, w, s1, s2);
-    weighted_rows<4, kRB>(base, oa, o1, o2, w, s1, s2);
-    weighted_rows<6, kRB>(base, oa, o1, o2, w, s1, s2);
-    return s1 > s2;
+    int acc = 0;                   // S_1 - S_2
+    weighted_rows<0, kRB>(base, oa, o1, o2, w, acc);
+    weighted_rows<2, kRB>(base, oa, o1, o2, w, acc);
+    weighted_rows<4, kRB>(base, oa, o1, o2, w, acc);
+    weighted_rows<6, kRB>(base, oa, o1, o2, w, acc);
+    return acc > 0;
 }
 
 template <bool kTable, int kW>
