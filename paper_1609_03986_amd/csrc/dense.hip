@@ -63,13 +63,16 @@ __device__ __forceinline__ int lane_next(int v)
     return __builtin_amdgcn_mov_dpp(v, 0x130, 0xF, 0xF, true);
 }
 
-// Sum of v over lanes l .. l + 6 (only lanes 0 .. 57 are used), by a chain
-// of whole-wavefront DPP shifts: no LDS traffic and short latency.
+// Sum of v over lanes l .. l + 6 (only lanes 0 .. 57 are used), in Horner
+// form t = v + (t of the next lane), six times: each step is one add whose
+// shifted operand comes through DPP (whole-wavefront shift), with no LDS
+// traffic.
 __device__ __forceinline__ int sum7_down(int v)
 {
-    const int a1 = lane_next(v), a2 = lane_next(a1), a3 = lane_next(a2);
-    const int a4 = lane_next(a3), a5 = lane_next(a4), a6 = lane_next(a5);
-    return v + a1 + a2 + a3 + a4 + a5 + a6;
+    int t = v;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) t = v + lane_next(t);
+    return t;
 }
 
 __global__ __launch_bounds__(kDThreads) void dense_extract_kernel(
