@@ -392,7 +392,19 @@ SplitKernel split_kernel(int path)
                                          : SplitKernel::kPopcount;
 }
 
-KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuning &tune)
+// Split plan of a single-pair call.  The base choice fills the GPU's
+// workgroup slots once (slots / query groups splits), raised to what the
+// split-local index needs and capped at 8 tiles per split.  Work items
+// (query group, split) then run in rounds of `slots`, each costing about its
+// split's tiles; when the base count leaves the last round partly empty (the
+// index raised it, or the query groups alone exceed the slots), a larger
+// count can spread the same tiles over fuller rounds.  Over counts up to 4x
+// the base (at most 512 more), within `partial_cap` bytes of partials, the
+// smallest count whose rounds x tiles per split is within 2% of the least is
+// taken (more splits also mean more merge work and partials), unless the
+// base itself is.
+KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuning &tune,
+                 size_t partial_cap)
 {
     KnnPlan p;
     p.nq = nq;
@@ -415,7 +427,27 @@ KnnPlan plan_knn(int64_t nq, int64_t nt, int path, int num_cus, const latch_tuni
     const int64_t min_by_index = (nt + max_rows - 1) / max_rows;
     if (nsplit < min_by_index) nsplit = min_by_index;
     if (nsplit > kMaxSplits) nsplit = kMaxSplits;
-    const int64_t tiles_per_split = (tiles + nsplit - 1) / nsplit;
+    auto tiles_per = [&](int64_t n) { return (tiles + n - 1) / n; };
+    auto cost = [&](int64_t n) {                       // rounds x tiles per split
+        const int64_t tps = tiles_per(n), used = (tiles + tps - 1) / tps;
+        return (qgroups * used + slots - 1) / slots * tps;
+    };
+    const int64_t n_hi = std::min({(int64_t)kMaxSplits, std::max(nsplit, max_by_size), 4 * nsplit + 8,
+                                   nsplit + 512});
+    const int64_t base_cost = cost(nsplit);
+    int64_t least = base_cost, top = nsplit;
+    for (int64_t n = nsplit + 1; n <= n_hi; ++n) {
+        if ((size_t)n * (size_t)nq * 2 * sizeof(uint64_t) > partial_cap) break;
+        least = std::min(least, cost(n));
+        top = n;
+    }
+    if (base_cost * 50 > least * 51)
+        for (int64_t n = nsplit + 1; n <= top; ++n)
+            if (cost(n) * 50 <= least * 51) {
+                nsplit = n;
+                break;
+            }
+    const int64_t tiles_per_split = tiles_per(nsplit);
     p.split_rows = tiles_per_split * kTileRows;
     p.nsplit = (int)((tiles + tiles_per_split - 1) / tiles_per_split);
     return p;
@@ -637,7 +669,8 @@ int knn_call(latch_handle h, const uint32_t *query_dev, int64_t nq, const uint32
     a.query = query_dev;
     a.train = train_dev;
     a.shape = knn_shape(h->tuning);
-    a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning);
+    a.plan = plan_knn(nq, nt, path, h->num_cus, h->tuning,
+                      noalloc ? (size_t)LATCH_NOALLOC_SCRATCH_BYTES : SIZE_MAX);
     a.partial = nullptr;
     a.k = k;
     a.ratio = ratio;
@@ -1035,7 +1068,7 @@ int hamming_knn_workspace_size(latch_handle h, int64_t nq, int64_t nt, int path,
     if (path < LATCH_PATH_AUTO || path > LATCH_PATH_MFMA_FP4)
         return fail(h, LATCH_EINVAL, "unknown path %d", path);
     path = resolve_path(h, path, nq, nt);
-    *bytes = nq == 0 ? 0 : knn_workspace_bytes(plan_knn(nq, nt, path, h->num_cus, h->tuning));
+    *bytes = nq == 0 ? 0 : knn_workspace_bytes(plan_knn(nq, nt, path, h->num_cus, h->tuning, SIZE_MAX));
     return LATCH_OK;
 }
 

@@ -119,7 +119,7 @@ int main()
                     const int run = resolve_path(&probe, path, nq, nt);
                     check(run == path || (path == LATCH_PATH_MFMA_FP4 && run == LATCH_PATH_MFMA),
                           "resolved path");
-                    const KnnPlan p = plan_knn(nq, nt, run, 256, tune);
+                    const KnnPlan p = plan_knn(nq, nt, run, 256, tune, SIZE_MAX);
                     check(p.nsplit <= kMaxSplits && p.split_rows <= kMaxSplitRows, "plan limits");
                     check(p.nsplit >= 1 && p.split_rows >= kTileRows && p.split_rows % kTileRows == 0,
                           "plan shape");
