@@ -87,7 +87,11 @@ __device__ __forceinline__ void issue_samples(const Keypoint &k, int tid,
     }
 }
 
-// Pixel (i, j) goes to element j - s of row i of copy s, s = 0..3 (j >= s).
+// Pixel (i, j) goes to element j - s of row i of copy s, s = 0..3.  For
+// j < s that is element W + 8 + j - s of the row before (or, for i = 0, of
+// the previous copy's spare row): one of the last three spare elements of a
+// row, which no patch read reaches (a patch row reads elements up to W), so
+// the writes need no condition.
 template <int kW>
 __device__ __forceinline__ void write_window(uint8_t *lds, int tid, const uint32_t (&g)[WGeom<kW>::kSamples])
 {
@@ -100,7 +104,7 @@ __device__ __forceinline__ void write_window(uint8_t *lds, int tid, const uint32
         const uint16_t v = (uint16_t)g[m];
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-            if (j >= s) *reinterpret_cast<uint16_t *>(row + s * G::kCopyBytes - 2 * s) = v;
+            *reinterpret_cast<uint16_t *>(row + s * G::kCopyBytes - 2 * s) = v;
     }
 }
 
@@ -205,7 +209,8 @@ __global__ __launch_bounds__(kWThreads) void extract_weighted_kernel(
     const int lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
 
-    // The spare columns and row stay zero (they meet zero weights only).
+    // The spare columns and row that patch reads reach stay zero (they meet
+    // zero weights only).
     for (int i = tid; i < G::kLds / 4; i += kWThreads) reinterpret_cast<uint32_t *>(lds)[i] = 0u;
 
     // This lane's slots in rounds 0 and 1, and the slots of its output bits
