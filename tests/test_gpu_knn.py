@@ -170,3 +170,32 @@ def test_fp4_split_boundaries(torch_cuda, lat):
         T = synth.random_descriptors(g, nt, p_one=0.02)
         T[-1] = T[0]                                  # an exact tie across the whole set
         check(torch_cuda, lat, Q, T, paths=("fp4", "mfma"))
+
+
+@pytest.mark.parametrize("path", ["fp4", "mfma"])
+@pytest.mark.parametrize("nq,nt", [(20_000, 20_000), (100_000, 100_000)])
+def test_split_counts_that_fill_the_last_round(torch_cuda, lat, nq, nt, path):
+    """Shapes where the split planner takes more splits than the base count
+    to fill the last round of work items (20k x 20k: 19 splits on the MXFP4
+    path instead of 9; 100k x 100k: 21 instead of 7): every row equals the
+    batched matcher, which scans each pair's whole train range with no splits
+    or merge, and a sample equals the oracle."""
+    from paper_1609_03986_amd.binding import pair_table
+    torch = torch_cuda
+    g = np.random.default_rng(nq + nt)
+    Q = synth.random_descriptors(g, nq, 0.3)
+    T = synth.random_descriptors(g, nt, 0.3)
+    T[7:17] = T[nt - 10:]                            # duplicate rows: ties across splits
+    q, t = to_dev(torch, Q), to_dev(torch, T)
+    lat.reserve(lat.knn_workspace_size(nq, nt, path))
+    idx, dist, acc = lat.knn(q, t, path=path)
+    both = torch.cat([q, t])
+    b_idx, b_dist, b_acc = lat.knn_batch(both, both, pair_table([(0, nq, nq, nt, 0)]), nq, path=path)
+    torch.cuda.synchronize()
+    assert lat.check_errors(clear=True) == 0
+    assert torch.equal(idx, b_idx) and torch.equal(dist, b_dist) and torch.equal(acc, b_acc)
+    sel = np.arange(0, nq, 997)
+    wi, wd, wa = oracle.knn(Q[sel], T)
+    assert np.array_equal(idx.cpu().numpy()[sel], wi)
+    assert np.array_equal(dist.cpu().numpy()[sel], wd)
+    assert np.array_equal(acc.cpu().numpy()[sel], wa)
