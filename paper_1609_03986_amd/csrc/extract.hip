@@ -36,7 +36,7 @@
 //
 // The paper's CUDA kernel (Sec. 3.2) spreads one descriptor over 32 warps of
 // a 1024-thread block with float32 patches in shared memory; here two 64-lane
-// wavefronts share a 19.3 KB byte window (eight per CU, four wavefronts per
+// wavefronts share a 19.4 KB byte window (eight per CU, four wavefronts per
 // SIMD) and synchronise twice per descriptor.
 #include "internal.h"
 
