@@ -751,6 +751,14 @@ def versions(torch):
     except OSError:
         out["amdgpu_driver"] = None
     try:
+        # The HIP runtime's own report of the driver stack it runs on.
+        import ctypes
+        v = ctypes.c_int(0)
+        rc = ctypes.CDLL("libamdhip64.so").hipDriverGetVersion(ctypes.byref(v))
+        out["hip_driver_version"] = v.value if rc == 0 else None
+    except (OSError, AttributeError):
+        out["hip_driver_version"] = None
+    try:
         from paper_1609_03986_amd.binding import latch_version
         out["library"] = latch_version()
     except Exception:
