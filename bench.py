@@ -24,6 +24,7 @@ per-pixel descriptors with windowed matching.
     python bench.py [--gpus 1] [--steps 20] [--warmup 5]
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -111,7 +112,6 @@ def recorded_traffic(kernel, workload):
     profiles/traffic.json for this kernel on this workload, or None when
     missing or when the kernel's source has changed since the counters were
     taken."""
-    import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["kernels"]
         rec = rec["%s@%s" % (kernel, workload)]
@@ -424,6 +424,8 @@ def main():
     # --- The SfM batch and its captured plan. ---
     log("generating the SfM batch")
     imgs, kps = synth.sfm_workload()
+    inputs = {"triplets_sha256": digest([trip]),
+              "sfm": {"images_sha256": digest(imgs), "keypoints_sha256": digest(kps)}}
     sfm = Batch(torch, lat, imgs, kps, args.path)
     total, n_pairs = sfm.total, sfm.n_pairs
     # One run of the plain form and of the plan on the same inputs: the two
@@ -503,6 +505,7 @@ def main():
     if "uneven" in comps:
         log("uneven batch")
         u_imgs, u_kps = synth.uneven_workload()
+        inputs["uneven"] = {"images_sha256": digest(u_imgs), "keypoints_sha256": digest(u_kps)}
         ub = Batch(torch, lat, u_imgs, u_kps, args.path)
         u_run, u_out = ub.per_image_form()
         u_run()
@@ -583,10 +586,20 @@ def main():
         "cpu_baseline": cpu,
         "paper": PAPER,
         "components": components,
+        "inputs": inputs,
         "versions": versions(torch),
     }
     print(json.dumps(out), flush=True)
     lat.close()
+
+
+def digest(arrays):
+    """SHA-256 over the bytes of the given arrays, in order (the record of the
+    seeded synthetic inputs a run used)."""
+    h = hashlib.sha256()
+    for a in arrays:
+        h.update(np.ascontiguousarray(a).tobytes())
+    return h.hexdigest()
 
 
 def serving_component(torch, trip, rates=((50, 200), (200, 400), (800, 400)), slots=4):
@@ -602,7 +615,7 @@ def serving_component(torch, trip, rates=((50, 200), (200, 400), (800, 400)), sl
     sched = serve.Scheduler(ex, slots, 8 << 30, db.shape[0])
     sched.run(serve.max_requests(slots, pool))
     out = {"db_rows": int(db.shape[0]), "slots": slots, "slot_workspace_bytes": ex.reserved,
-           "rates": []}
+           "db_sha256": digest([db.cpu().numpy()]), "rates": []}
     for qps, n in rates:
         results, rejected, stats = sched.run(serve.make_requests(n, qps, pool, seed=int(qps)))
         pairs = sum(len(r.idx) for r in results) * db.shape[0]

@@ -324,6 +324,8 @@ def main(argv=None):
     trip = synth.triplet_table()
     builder = Latch(trip)
     db = build_database(builder, args.db_rows)
+    import hashlib
+    db_sha256 = hashlib.sha256(db.cpu().numpy().tobytes()).hexdigest()   # record of the inputs
     pool = request_pool()
     ex = GpuExecutor(db, trip, args.slots, path=args.path)
     sched = Scheduler(ex, args.slots, int(args.hbm_budget_gb * 2 ** 30), args.db_rows,
@@ -336,7 +338,7 @@ def main(argv=None):
         pairs = sum(len(r.idx) for r in results) * args.db_rows
         stats.update({"offered_qps": qps, "db_rows": args.db_rows, "slots": args.slots,
                       "pairs_per_s": pairs / stats["wall_s"], "path": args.path,
-                      "slot_workspace_bytes": ex.reserved,
+                      "slot_workspace_bytes": ex.reserved, "db_sha256": db_sha256,
                       "tuning": "in-tree table" if ex.tuning is not None else "library default",
                       "timed_out": len(stats["timed_out"]), "cancelled": len(stats["cancelled"])})
         print(json.dumps(stats), flush=True)
