@@ -329,10 +329,12 @@ int hamming_knn(latch_handle h, const uint32_t *query_dev, int64_t nq,
  * split partials live in a static device array of LATCH_NOALLOC_SCRATCH_BYTES
  * that the library holds on every GPU it runs on until the process ends, not
  * in the handle's workspace: the call never allocates, frees or reserves, and
- * records no timing events.  The split plan is the one hamming_knn_workspace_size
- * prices; a call whose partials would exceed the scratch (16 bytes per
- * (query, train split) when the train rows are split) returns LATCH_ERANGE
- * and enqueues nothing.  Every call on one GPU shares that GPU's scratch:
+ * records no timing events.  The split plan is hamming_knn's (the one
+ * hamming_knn_workspace_size prices), except that the extra splits the
+ * planner may add to fill the last round of workgroups are taken only while
+ * the partials fit the scratch; a call whose partials exceed the scratch even
+ * without them (16 bytes per (query, train split) when the train rows are
+ * split) returns LATCH_ERANGE and enqueues nothing.  Every call on one GPU shares that GPU's scratch:
  * calls that overlap in time on one GPU (any handle, any stream) race, so
  * order them on one stream.  The scratch keeps the last call's contents;
  * nothing in it needs to start at zero.
