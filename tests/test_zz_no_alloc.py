@@ -127,6 +127,42 @@ def test_noalloc_refuses_more_than_its_scratch(torch_cuda, triplets):
         lat.close()
 
 
+def test_noalloc_keeps_extra_splits_within_its_scratch(torch_cuda, triplets):
+    """16,000 queries against 1,000,000 rows: the split planner of hamming_knn
+    adds splits beyond its base count to fill the last round of workgroups,
+    and their partials would exceed the scratch; the allocation-free call adds
+    only as many as fit.  It runs, and both give the same results (which never
+    depend on the split count), equal to the oracle on a sample."""
+    torch = torch_cuda
+    from paper_1609_03986_amd import binding
+    from paper_1609_03986_amd.binding import Latch
+    g = np.random.default_rng(41)
+    nq, nt = 16_000, 1_000_000
+    lat, ref = Latch(triplets), Latch(triplets)
+    try:
+        assert ref.knn_workspace_size(nq, nt, "fp4") > binding.NOALLOC_SCRATCH_BYTES
+        Q = synth.random_descriptors(g, nq)
+        T = synth.random_descriptors(g, nt)
+        Q[:20] = T[nt - 20:]                             # exact matches in the last split
+        q, t = to_dev(torch, Q), to_dev(torch, T)
+        idx, dist, acc = outputs(torch, nq)
+        assert raw_call(torch, "hamming_knn_noalloc", lat, q, t, idx, dist, acc, "fp4") == \
+            binding.LATCH_OK
+        ri, rd, ra = reference(torch, ref, q, t, "fp4")
+        torch.cuda.synchronize()
+        assert torch.equal(idx, ri) and torch.equal(dist, rd) and torch.equal(acc, ra)
+        sel = np.concatenate([np.arange(5), np.arange(20, nq, 1601)])
+        wi, wd, wa = oracle.knn(Q[sel], T)
+        assert np.array_equal(idx.cpu().numpy()[sel], wi)
+        assert np.array_equal(dist.cpu().numpy()[sel], wd)
+        assert np.array_equal(acc.cpu().numpy()[sel], wa)
+        assert lat.check_errors() == 0
+    finally:
+        torch.cuda.synchronize()
+        lat.close()
+        ref.close()
+
+
 def test_noalloc_captured_in_a_graph(torch_cuda, triplets):
     """Captured with no reservation at all; replays with new query contents
     and eager work between them, each equal to eager hamming_knn."""
